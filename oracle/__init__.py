@@ -1,0 +1,248 @@
+"""FP64 CPU oracle for the WASABI hologram path (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import
+this package.  It shares no code with the HIP library: the arithmetic lives in ``oracle.c``
+(plain loops, FP64), and this module only marshals numpy arrays into it.
+
+Paper: Shimobaba et al., "Fast, large-scale hologram calculation in wavelet domain".
+  * ``direct``          -- Eq.(1), optionally restricted to the PSF's circ() support.
+  * ``lut_geometry``    -- Sec. 2 step 1 (planes, PSF radius, N_r = gamma*pi*R^2).
+  * ``psf_table``       -- Sec. 2 step 1 (u_z = exp(ikr) circ(.)).
+  * ``haar_forward`` / ``haar_inverse`` -- Sec. 2 steps 1 and 3, Fig. 2(a) layout (Haar wavelet).
+  * ``build_lut``       -- Sec. 2 step 1 (transform + keep the N_r strongest coefficients).
+  * ``quantize``        -- depth discretisation and the 2^L grid that Eq.(2) needs.
+  * ``superpose``       -- Eq.(2) with the sub-hologram shift of the large-scale procedure.
+  * ``wasabi``          -- superpose followed by the inverse transform (Sec. 2 steps 2-4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+F32, F16, BF16, F64 = 0, 1, 2, 3
+FULL, CIRC = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain C, FP64, OpenMP over output rows)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC,
+                               "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.oracle_direct.argtypes = [P, I64, I32, I32, I64, I64, D, D, I32, P]
+    lib.oracle_direct.restype = None
+    lib.oracle_lut_geometry.argtypes = [D, D, D, D, I32, I32, I32, D, P, P, P, P]
+    lib.oracle_lut_geometry.restype = ctypes.c_int
+    lib.oracle_psf_table.argtypes = [D, D, I32, D, D, P]
+    lib.oracle_psf_table.restype = None
+    lib.oracle_haar_forward.argtypes = [P, I32, I32, I32]
+    lib.oracle_haar_forward.restype = None
+    lib.oracle_haar_inverse.argtypes = [P, I32, I32, I32]
+    lib.oracle_haar_inverse.restype = None
+    lib.oracle_select.argtypes = [P, I32, I64, P, P]
+    lib.oracle_select.restype = None
+    lib.oracle_round_value.argtypes = [D, I32]
+    lib.oracle_round_value.restype = D
+    lib.oracle_build_lut.argtypes = [D, D, I32, I32, P, P, P, P, P, I32, P, P]
+    lib.oracle_build_lut.restype = None
+    lib.oracle_quantize.argtypes = [P, I64, D, D, D, I32, I32, P, P, P, P]
+    lib.oracle_quantize.restype = None
+    lib.oracle_superpose.argtypes = [I32, P, P, P, P, P, P, P, P, I64, I64, I64, I32, I32, P]
+    lib.oracle_superpose.restype = None
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _complex_from(buf: np.ndarray, shape) -> np.ndarray:
+    return buf.view(np.complex128).reshape(shape)
+
+
+# ----------------------------------------------------------------------------------------------
+# Eq.(1)
+# ----------------------------------------------------------------------------------------------
+def direct(pts: np.ndarray, nx: int, ny: int, ox: int = 0, oy: int = 0, pitch: float = 1e-6,
+           wavelength: float = 633e-9, window: int = FULL) -> np.ndarray:
+    """u(x_h, y_h) = sum_j a_j exp(i 2 pi r_hj / lambda) on an ny x nx window (Eq.(1)).
+
+    pts: (n, 4) float64 {x, y, z, a}, metres.  window=CIRC restricts each point to its PSF disk.
+    """
+    lib = _load()
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 4)
+    out = np.zeros(2 * nx * ny, dtype=np.float64)
+    lib.oracle_direct(_p(pts), pts.shape[0], nx, ny, ox, oy, pitch, wavelength, window, _p(out))
+    return _complex_from(out, (ny, nx))
+
+
+# ----------------------------------------------------------------------------------------------
+# LUT (Sec. 2, step 1)
+# ----------------------------------------------------------------------------------------------
+@dataclass
+class LutParams:
+    wavelength: float = 633e-9
+    pitch: float = 1e-6
+    z_min: float = 0.1e-3
+    z_max: float = 1.5e-3
+    n_depth: int = 64
+    levels: int = 3
+    max_window: int = 1024
+    gamma: float = 0.05
+    value_dtype: int = F32
+
+
+@dataclass
+class Lut:
+    """Canonical LUT: plane d owns entries [off[d], off[d+1]) sorted by flat table index."""
+    params: LutParams
+    z: np.ndarray      # (n_depth,) plane depth z_d, metres
+    R: np.ndarray      # (n_depth,) PSF radius, pixels
+    W: np.ndarray      # (n_depth,) table side, int32
+    Nr: np.ndarray     # (n_depth,) kept coefficients, int64
+    off: np.ndarray    # (n_depth + 1,) int64
+    idx: np.ndarray    # (sum Nr,) int32 flat index row * W + col
+    val: np.ndarray    # (sum Nr,) complex128, already rounded to the storage dtype
+
+
+def lut_geometry(prm: LutParams):
+    lib = _load()
+    n = prm.n_depth
+    z = np.zeros(n); R = np.zeros(n)
+    W = np.zeros(n, dtype=np.int32); Nr = np.zeros(n, dtype=np.int64)
+    rc = lib.oracle_lut_geometry(prm.wavelength, prm.pitch, prm.z_min, prm.z_max, n, prm.levels,
+                                 prm.max_window, prm.gamma, _p(z), _p(R), _p(W), _p(Nr))
+    if rc != 0:
+        raise ValueError("a PSF table exceeds max_window")
+    return z, R, W, Nr
+
+
+def psf_table(z: float, R: float, W: int, pitch: float = 1e-6, wavelength: float = 633e-9):
+    lib = _load()
+    out = np.zeros(2 * W * W)
+    lib.oracle_psf_table(z, R, W, pitch, wavelength, _p(out))
+    return _complex_from(out, (W, W))
+
+
+def haar_forward(a: np.ndarray, levels: int) -> np.ndarray:
+    lib = _load()
+    b = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    h, w = b.shape
+    lib.oracle_haar_forward(_p(b), h, w, levels)
+    return b
+
+
+def haar_inverse(a: np.ndarray, levels: int) -> np.ndarray:
+    lib = _load()
+    b = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    h, w = b.shape
+    lib.oracle_haar_inverse(_p(b), h, w, levels)
+    return b
+
+
+def select(C: np.ndarray, Nr: int):
+    lib = _load()
+    C = np.ascontiguousarray(C, dtype=np.complex128)
+    W = C.shape[0]
+    idx = np.zeros(Nr, dtype=np.int32)
+    val = np.zeros(2 * Nr)
+    lib.oracle_select(_p(C), W, Nr, _p(idx), _p(val))
+    return idx, val.view(np.complex128)
+
+
+def round_value(v: float, dtype: int) -> float:
+    return _load().oracle_round_value(float(v), dtype)
+
+
+def build_lut(prm: LutParams) -> Lut:
+    lib = _load()
+    z, R, W, Nr = lut_geometry(prm)
+    off = np.zeros(prm.n_depth + 1, dtype=np.int64)
+    off[1:] = np.cumsum(Nr)
+    total = int(off[-1])
+    idx = np.zeros(total, dtype=np.int32)
+    val = np.zeros(2 * total)
+    lib.oracle_build_lut(prm.wavelength, prm.pitch, prm.n_depth, prm.levels, _p(z), _p(R), _p(W),
+                         _p(Nr), _p(off), prm.value_dtype, _p(idx), _p(val))
+    return Lut(prm, z, R, W, Nr, off, idx, val.view(np.complex128))
+
+
+# ----------------------------------------------------------------------------------------------
+# Points, Eq.(2), inverse transform
+# ----------------------------------------------------------------------------------------------
+@dataclass
+class Quantized:
+    x: np.ndarray  # int32 global pixel column, multiple of 2^L
+    y: np.ndarray  # int32 global pixel row
+    d: np.ndarray  # int32 plane, -1 = invalid
+    a: np.ndarray  # float64 amplitude
+
+
+def quantize(pts: np.ndarray, prm: LutParams) -> Quantized:
+    lib = _load()
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 4)
+    n = pts.shape[0]
+    qx = np.zeros(n, np.int32); qy = np.zeros(n, np.int32); qd = np.zeros(n, np.int32)
+    qa = np.zeros(n)
+    lib.oracle_quantize(_p(pts), n, prm.pitch, prm.z_min, prm.z_max, prm.n_depth, prm.levels,
+                        _p(qx), _p(qy), _p(qd), _p(qa))
+    return Quantized(qx, qy, qd, qa)
+
+
+def snapped_points(q: Quantized, lut: Lut) -> np.ndarray:
+    """Quantised points back in metres {x, y, z_d, a} for the direct sum (invalid ones dropped)."""
+    ok = q.d >= 0
+    p = lut.params.pitch
+    return np.stack([q.x[ok] * p, q.y[ok] * p, lut.z[q.d[ok]], q.a[ok]], axis=1)
+
+
+def superpose(lut: Lut, q: Quantized, X0: int, Y0: int, nx: int, ny: int) -> np.ndarray:
+    lib = _load()
+    psi = np.zeros(2 * nx * ny)
+    vals = np.ascontiguousarray(lut.val).view(np.float64)
+    x = np.ascontiguousarray(q.x, np.int32); y = np.ascontiguousarray(q.y, np.int32)
+    d = np.ascontiguousarray(q.d, np.int32); a = np.ascontiguousarray(q.a, np.float64)
+    lib.oracle_superpose(lut.params.levels, _p(lut.W), _p(lut.off), _p(lut.idx), _p(vals),
+                         _p(x), _p(y), _p(d), _p(a), x.shape[0], X0, Y0, nx, ny, _p(psi))
+    return _complex_from(psi, (ny, nx))
+
+
+def wasabi(lut: Lut, q: Quantized, X0: int, Y0: int, nx: int, ny: int) -> np.ndarray:
+    """Hologram window (Sec. 2 large-scale steps 2-4): Eq.(2) then the inverse transform."""
+    return haar_inverse(superpose(lut, q, X0, Y0, nx, ny), lut.params.levels)
+
+
+# ----------------------------------------------------------------------------------------------
+# Quality measures (definitions of the design notes; the paper prints none)
+# ----------------------------------------------------------------------------------------------
+def rel_l2(u: np.ndarray, ref: np.ndarray) -> float:
+    return float(np.linalg.norm((u - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def psnr(u: np.ndarray, ref: np.ndarray) -> float:
+    """10 log10(max|ref|^2 / mean|u - ref|^2) on the complex field."""
+    mse = float(np.mean(np.abs(u - ref) ** 2))
+    peak = float(np.max(np.abs(ref)) ** 2)
+    return float("inf") if mse == 0 else 10.0 * np.log10(peak / mse)
