@@ -1,0 +1,183 @@
+/*
+ * cgh.h -- C ABI of the MI355X (gfx950) WASABI hologram library, libcgh.so.
+ *
+ * Method: T. Shimobaba et al., "Fast, large-scale hologram calculation in wavelet domain"
+ * (WAvelet ShrinkAge-Based superpositIon).  A hologram of N point sources is
+ *     u(x_h, y_h) = sum_j a_j exp(i 2 pi r_hj / lambda)                          (Eq.(1))
+ * WASABI computes it by superposing, in the wavelet domain, the N_r strongest wavelet
+ * coefficients of each point's pre-computed PSF at level-scaled shifts (Eq.(2)), then running one
+ * inverse wavelet transform (Sec. 2, steps 1-3); large holograms are split into sub-holograms
+ * (Sec. 2, large-scale procedure).  The wavelet here is the orthonormal Haar wavelet.
+ *
+ * Conventions for every call
+ *  - Pointers named *_dev / buffers documented as "device" are device memory of the current HIP
+ *    device; the caller owns them and the library never frees them.  Host buffers are named as such.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls enqueue work on
+ *    it and return without waiting, except where a call says it synchronises.
+ *  - Coordinates: pixel (i, j) of a window with origin (ox, oy) is global pixel (ox + j, oy + i);
+ *    row = y, column = x; the centre of global pixel (0, 0) is the physical origin.
+ *  - Complex data is interleaved (re, im): complex64 = 2 x float, complex128 = 2 x double.
+ *  - Every call validates its arguments before launching anything and returns CGH_OK or a negative
+ *    cgh_status; cgh_last_error() then gives a message (thread-local).  A kernel launch failure is
+ *    reported by the call that launched it; faults that occur later surface at the caller's next
+ *    synchronisation of the stream.
+ *  - Scratch memory is taken from HIP's stream-ordered pool (hipMallocAsync on `stream`) and given
+ *    back on the same stream before the call returns.
+ */
+#ifndef CGH_H
+#define CGH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CGH_OK = 0,
+    CGH_EINVAL = -1,     /* an argument is out of range or inconsistent                      */
+    CGH_ENOMEM = -2,     /* device memory (or the server's memory budget) cannot hold the job */
+    CGH_EHIP = -3,       /* a HIP runtime call failed                                         */
+    CGH_EAGAIN = -4,     /* the result is not ready yet                                       */
+    CGH_ENOTFOUND = -5,  /* unknown ticket                                                    */
+    CGH_ETIMEDOUT = -6,  /* a wait timed out                                                  */
+    CGH_ECANCELED = -7   /* the job was cancelled or its server destroyed                     */
+} cgh_status;
+
+enum { CGH_C64 = 0, CGH_C128 = 1 };             /* complex output type                         */
+enum { CGH_F32 = 0, CGH_F16 = 1, CGH_BF16 = 2 };/* LUT value storage (rounded to nearest even) */
+enum { CGH_FULL = 0, CGH_CIRC = 1 };            /* direct-sum window                           */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *cgh_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Eq.(1): direct superposition of N point sources.
+ *   pts_dev : device, n x 4 double {x, y, z, a}: metres, z > 0 (distance to the hologram plane),
+ *             a = amplitude (the paper's "light intensity" a_j enters Eq.(1) linearly).
+ *   window  : CGH_FULL -- every point reaches every pixel (Eq.(1) as written);
+ *             CGH_CIRC -- a point reaches only the pixels inside its PSF disk,
+ *             (x_h - x_j)^2 + (y_h - y_j)^2 < (z_j tan theta)^2, sin theta = lambda / (2 pitch)
+ *             (the circ() support of the pre-computed PSF, Sec. 2 step 1).
+ *   out_dev : device, ny rows of nx complex values, row stride ld_out elements (ld_out >= nx);
+ *             overwritten.  CGH_C64: phase from FP64 r / lambda, FP32 sine/cosine, FP32 sums.
+ *             CGH_C128: FP64 throughout.
+ * Errors: CGH_EINVAL (n < 0, nx/ny < 1, ld_out < nx, pitch/wavelength not > 0,
+ *         wavelength >= 2 pitch, bad enum, NULL pointer with n > 0), CGH_EHIP.  n = 0 writes zeros.
+ * ------------------------------------------------------------------------------------------- */
+int cgh_direct(const double *pts_dev, int64_t n, int32_t nx, int32_t ny, int64_t ox, int64_t oy,
+               double pitch, double wavelength, int32_t window, int32_t out_dtype, void *out_dev,
+               int64_t ld_out, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Coefficient LUT (Sec. 2, step 1: pre-computation).
+ * Plane d (0 <= d < n_depth) sits at z_d = z_min + (d + 1/2) dz, dz = (z_max - z_min) / n_depth.
+ * Its PSF exp(i 2 pi r / lambda) circ() has radius R_d = z_d tan(theta) / pitch pixels and is
+ * sampled on a W_d x W_d table centred on pixel W_d / 2, W_d = the smallest multiple of 2^(L+1)
+ * with W_d >= 2 floor(R_d) + 2.  The table gets an L-level orthonormal Haar transform, and the
+ * N_r(d) = ceil(gamma pi R_d^2) coefficients of largest magnitude (clamped to [1, W_d^2]; all
+ * W_d^2 when gamma >= 1) are kept, values rounded to `value_dtype`.  Magnitude ties are broken
+ * by the library's internal coefficient order, so two correct LUTs may differ at the threshold.
+ * The PSF phase, transform and selection are computed in FP64.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+    double wavelength;   /* metres, 0 < wavelength < 2 pitch                                  */
+    double pitch;        /* hologram sampling pitch, metres                                    */
+    double z_min, z_max; /* depth range, metres, 0 < z_min < z_max                             */
+    int32_t n_depth;     /* number of planes, 1 .. 65536                                       */
+    int32_t levels;      /* wavelet levels L, 1 .. 6                                           */
+    int32_t max_window;  /* largest allowed table side; every W_d must fit (else CGH_EINVAL),
+                            and W_d <= 2^(16 - L)                                              */
+    int32_t value_dtype; /* CGH_F32, CGH_F16 or CGH_BF16                                       */
+    double gamma;        /* selectivity, > 0                                                   */
+} wasabi_lut_params;
+
+typedef struct wasabi_lut wasabi_lut; /* opaque, library-owned, device-resident */
+
+/* Build the LUT on the current device.  Synchronises `stream` once (to size the tables).
+ * Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP.  On error *out is NULL. */
+int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, void *stream);
+
+/* Build the device LUT from host arrays in the canonical layout: plane d owns entries
+ * [off[d], off[d+1]) (off: n_depth + 1 int64, off[0] = 0), each an int32 flat table index
+ * idx = row * W_d + col of the plane's Mallat-layout table (sorted ascending, no repeats) and a
+ * complex value val[2k], val[2k+1] (double, rounded here to value_dtype).  The plane geometry
+ * comes from `prm`; gamma is ignored.  Synchronous.  Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
+int wasabi_lut_import(const wasabi_lut_params *prm, const int64_t *off_host,
+                      const int32_t *idx_host, const double *val_host, wasabi_lut **out);
+
+/* Sizes of the LUT.  Any output pointer may be NULL; per-plane arrays hold n_depth values (host). */
+int wasabi_lut_info(const wasabi_lut *lut, int32_t *n_depth, int64_t *total_entries,
+                    int64_t *device_bytes, double *z_host, double *R_host, int32_t *W_host,
+                    int64_t *Nr_host);
+
+/* Copy the LUT to host arrays in the canonical layout above (off: n_depth + 1, idx/val: total
+ * entries; val as double pairs holding the stored, rounded values).  Synchronous. */
+int wasabi_lut_export(const wasabi_lut *lut, int64_t *off_host, int32_t *idx_host, double *val_host);
+
+/* Release the LUT's device memory (waits for the device first).  NULL is accepted. */
+void wasabi_lut_free(wasabi_lut *lut);
+
+/* ---------------------------------------------------------------------------------------------
+ * Points for the wavelet path.  x, y: global pixel column / row, multiples of 2^L (superposition
+ * floors other values to the grid); depth: plane index, -1 = invalid (contributes nothing);
+ * a: amplitude.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t x, y, depth;
+    float a;
+} wasabi_point;
+
+/* Depth discretisation (Sec. 2, step 1) and the 2^L position grid that makes the level-scaled
+ * shift of Eq.(2) an integer: x/pitch and y/pitch go to the nearest multiple of 2^L (ties
+ * upward), z to plane floor((z - z_min) / dz) (z = z_max -> the last plane).  A point with z
+ * outside [z_min, z_max], a non-finite value, or a snapped position beyond +-2^30 gets depth -1.
+ *   pts_dev : device, n x 4 double {x, y, z, a} metres (as for cgh_direct).
+ *   out_dev : device, n wasabi_point.
+ * Errors: CGH_EINVAL, CGH_EHIP. */
+int wasabi_quantize(const wasabi_lut *lut, const double *pts_dev, int64_t n,
+                    wasabi_point *out_dev, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Eq.(2) on one sub-hologram (Sec. 2, large-scale steps 2-3): the ny x nx wavelet field psi of
+ * the window whose pixel (0,0) is global pixel (ox, oy), i.e. points enter with
+ * x'_j = x_j - ox, y'_j = y_j - oy.  Every kept coefficient of every valid point is added at its
+ * level-scaled position; coefficients that land outside the window are dropped (exact for
+ * Haar: the result equals the same window of a larger hologram).
+ *   psi_dev : device, ny x nx complex64 in Mallat layout (level-l bands of (ny>>l) x (nx>>l):
+ *             H at (0, nx>>l), V at (ny>>l, 0), D at (ny>>l, nx>>l), scaling band at (0, 0)),
+ *             overwritten.  FP32 accumulation.
+ * Requires ox, oy, nx, ny multiples of 2^L, nx, ny >= 2^L.
+ * Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
+int wasabi_superpose(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t n, int64_t ox,
+                     int64_t oy, int32_t nx, int32_t ny, void *psi_dev, void *stream);
+
+/* Inverse L-level orthonormal Haar transform (Sec. 2, step 3): psi (ny x nx complex64, Mallat
+ * layout, contiguous) -> u (ny rows of nx complex64, row stride ld_u elements).  u must not
+ * overlap psi.  Requires nx, ny multiples of 2^L.  Errors: CGH_EINVAL, CGH_EHIP. */
+int wasabi_idwt(const void *psi_dev, int32_t nx, int32_t ny, int32_t levels, void *u_dev,
+                int64_t ld_u, void *stream);
+
+/* Large-scale procedure (Sec. 2, steps 2-4): the ny x nx hologram window at global (ox, oy),
+ * computed as sub-holograms of at most sub x sub pixels (sub = 0: one sub-hologram), each by
+ * wasabi_superpose into a scratch wavelet field followed by wasabi_idwt into its part of u.
+ *   u_dev : device, ny rows of nx complex64, row stride ld_u >= nx; overwritten.
+ * Requires ox, oy, nx, ny and sub multiples of 2^L.  Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
+int wasabi_hologram(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t n, int64_t ox,
+                    int64_t oy, int32_t nx, int32_t ny, int32_t sub, void *u_dev, int64_t ld_u,
+                    void *stream);
+
+/* Same result as wasabi_hologram, computed tile by tile: each tile's Haar blocks are superposed
+ * (Eq.(2)) and inverted (Sec. 2, step 3) inside on-chip memory, so the wavelet field never goes
+ * to device memory.  Exact reordering for Haar, whose 2^L x 2^L blocks are independent.
+ * Same arguments and errors as wasabi_hologram without `sub`. */
+int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t n,
+                          int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *u_dev,
+                          int64_t ld_u, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGH_H */

@@ -1,0 +1,272 @@
+"""Python binding of libcgh.so, the MI355X (gfx950) WASABI hologram library.
+
+Argument marshalling only: every step runs in the library's HIP kernels.  Tensors are torch
+tensors on the current HIP device; calls run on ``torch.cuda.current_stream()``.  The names follow
+the C ABI in ``include/cgh.h``:
+
+  cgh_direct              Eq.(1), direct superposition (FULL or CIRC window)
+  wasabi_build_lut        Sec. 2 step 1, PSF tables -> Haar -> N_r strongest coefficients
+  wasabi_lut_import       the same LUT object from canonical host arrays
+  wasabi_quantize         depth planes and the 2^L position grid
+  wasabi_superpose        Eq.(2) on one sub-hologram, wavelet field in Mallat layout
+  wasabi_idwt             inverse Haar transform (Sec. 2 step 3)
+  wasabi_hologram         sub-hologram procedure (Sec. 2, large-scale steps 2-4)
+  wasabi_hologram_fused   the same, tile by tile in on-chip memory
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgh.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "cgh.h")
+
+CGH_OK, CGH_EINVAL, CGH_ENOMEM, CGH_EHIP, CGH_EAGAIN = 0, -1, -2, -3, -4
+CGH_ENOTFOUND, CGH_ETIMEDOUT, CGH_ECANCELED = -5, -6, -7
+C64, C128 = 0, 1
+F32, F16, BF16 = 0, 1, 2
+FULL, CIRC = 0, 1
+
+
+class CghError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("cgh error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _LutParams(ctypes.Structure):
+    _fields_ = [("wavelength", ctypes.c_double), ("pitch", ctypes.c_double),
+                ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
+                ("n_depth", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("max_window", ctypes.c_int32), ("value_dtype", ctypes.c_int32),
+                ("gamma", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libcgh.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcgh.so is not built (run `python paper_1708_04233_amd/build.py`)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "cgh_last_error": ([], ctypes.c_char_p),
+        "cgh_direct": ([P, I64, I32, I32, I64, I64, D, D, I32, I32, P, I64, P], ctypes.c_int),
+        "wasabi_build_lut": ([ctypes.POINTER(_LutParams), ctypes.POINTER(P), P], ctypes.c_int),
+        "wasabi_lut_import": ([ctypes.POINTER(_LutParams), P, P, P, ctypes.POINTER(P)], ctypes.c_int),
+        "wasabi_lut_info": ([P, P, P, P, P, P, P, P], ctypes.c_int),
+        "wasabi_lut_export": ([P, P, P, P], ctypes.c_int),
+        "wasabi_lut_free": ([P], None),
+        "wasabi_quantize": ([P, P, I64, P, P], ctypes.c_int),
+        "wasabi_superpose": ([P, P, I64, I64, I64, I32, I32, P, P], ctypes.c_int),
+        "wasabi_idwt": ([P, I32, I32, I32, P, I64, P], ctypes.c_int),
+        "wasabi_hologram": ([P, P, I64, I64, I64, I32, I32, I32, P, I64, P], ctypes.c_int),
+        "wasabi_hologram_fused": ([P, P, I64, I64, I64, I32, I32, P, I64, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/cgh.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) -
+                  {"if", "while", "for", "return", "sizeof"})
+
+
+def _check(rc: int):
+    if rc != CGH_OK:
+        raise CghError(rc, load().cgh_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError("%s must be a tensor on the GPU" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------------------------
+def cgh_direct(pts: torch.Tensor, nx: int, ny: int, ox: int = 0, oy: int = 0,
+               pitch: float = 1e-6, wavelength: float = 633e-9, window: int = FULL,
+               out: torch.Tensor | None = None, out_dtype=torch.complex64) -> torch.Tensor:
+    """Eq.(1) on the ny x nx window at global pixel (ox, oy); pts (n, 4) float64 {x, y, z, a}."""
+    n = pts.shape[0]
+    if out is None:
+        out = torch.empty((ny, nx), dtype=out_dtype, device=pts.device)
+    if out.dim() != 2 or out.shape[1] < nx or out.shape[0] != ny or out.stride(1) != 1:
+        raise ValueError("out must be (ny, >=nx) with unit column stride")
+    code = {torch.complex64: C64, torch.complex128: C128}[out.dtype]
+    pp = _dev(pts, "pts", torch.float64, (n, 4))
+    _check(load().cgh_direct(pp, n, nx, ny, ox, oy, pitch, wavelength, window, code,
+                             ctypes.c_void_p(out.data_ptr()), out.stride(0), _stream()))
+    return out
+
+
+@dataclass
+class LutParams:
+    wavelength: float = 633e-9
+    pitch: float = 1e-6
+    z_min: float = 0.1e-3
+    z_max: float = 1.5e-3
+    n_depth: int = 64
+    levels: int = 3
+    max_window: int = 1024
+    gamma: float = 0.05
+    value_dtype: int = F32
+
+    def c(self) -> _LutParams:
+        return _LutParams(self.wavelength, self.pitch, self.z_min, self.z_max, self.n_depth,
+                          self.levels, self.max_window, self.value_dtype, self.gamma)
+
+
+class Lut:
+    """Device-resident coefficient LUT (owns the library handle)."""
+
+    def __init__(self, handle: ctypes.c_void_p, params: LutParams):
+        self.handle = handle
+        self.params = params
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.wasabi_lut_free(self.handle)
+            self.handle = None
+
+    def info(self) -> dict:
+        lib = load()
+        nd = ctypes.c_int32()
+        tot = ctypes.c_int64()
+        dev_bytes = ctypes.c_int64()
+        _check(lib.wasabi_lut_info(self.handle, ctypes.byref(nd), ctypes.byref(tot),
+                                   ctypes.byref(dev_bytes), None, None, None, None))
+        n = nd.value
+        z = np.zeros(n); R = np.zeros(n)
+        W = np.zeros(n, np.int32); Nr = np.zeros(n, np.int64)
+        _check(lib.wasabi_lut_info(self.handle, None, None, None, z.ctypes.data, R.ctypes.data,
+                                   W.ctypes.data, Nr.ctypes.data))
+        return dict(n_depth=n, total_entries=tot.value, device_bytes=dev_bytes.value, z=z, R=R,
+                    W=W, Nr=Nr)
+
+    def export(self):
+        """(off, idx, val): canonical layout, val complex128 holding the stored values."""
+        inf = self.info()
+        tot = inf["total_entries"]
+        off = np.zeros(inf["n_depth"] + 1, np.int64)
+        idx = np.zeros(max(tot, 1), np.int32)
+        val = np.zeros(2 * max(tot, 1))
+        _check(load().wasabi_lut_export(self.handle, off.ctypes.data, idx.ctypes.data, val.ctypes.data))
+        return off, idx[:tot], val.view(np.complex128)[:tot]
+
+
+def wasabi_build_lut(params: LutParams) -> Lut:
+    h = ctypes.c_void_p()
+    prm = params.c()
+    _check(load().wasabi_build_lut(ctypes.byref(prm), ctypes.byref(h), _stream()))
+    return Lut(h, params)
+
+
+def wasabi_lut_import(params: LutParams, off: np.ndarray, idx: np.ndarray, val: np.ndarray) -> Lut:
+    off = np.ascontiguousarray(off, np.int64)
+    idx = np.ascontiguousarray(idx, np.int32)
+    v = np.ascontiguousarray(np.asarray(val, np.complex128)).view(np.float64)
+    if idx.size == 0:
+        idx = np.zeros(1, np.int32)
+        v = np.zeros(2)
+    h = ctypes.c_void_p()
+    prm = params.c()
+    torch.cuda.current_stream().synchronize()
+    _check(load().wasabi_lut_import(ctypes.byref(prm), off.ctypes.data, idx.ctypes.data,
+                                    v.ctypes.data, ctypes.byref(h)))
+    return Lut(h, params)
+
+
+def points_tensor(n: int, device="cuda") -> torch.Tensor:
+    """Storage for n wasabi_point records {int32 x, y, depth; float32 a} as an (n, 4) int32 tensor."""
+    return torch.empty((n, 4), dtype=torch.int32, device=device)
+
+
+def point_amplitudes(q: torch.Tensor) -> torch.Tensor:
+    return q[:, 3].contiguous().view(torch.float32)
+
+
+def wasabi_quantize(lut: Lut, pts: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    n = pts.shape[0]
+    if out is None:
+        out = points_tensor(n, pts.device)
+    pp = _dev(pts, "pts", torch.float64, (n, 4))
+    _check(load().wasabi_quantize(lut.handle, pp, n, _dev(out, "out", torch.int32, (n, 4)), _stream()))
+    return out
+
+
+def wasabi_superpose(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, ny: int,
+                     psi: torch.Tensor | None = None) -> torch.Tensor:
+    n = q.shape[0]
+    if psi is None:
+        psi = torch.empty((ny, nx), dtype=torch.complex64, device=q.device)
+    _check(load().wasabi_superpose(lut.handle, _dev(q, "points", torch.int32, (n, 4)), n, ox, oy,
+                                   nx, ny, _dev(psi, "psi", torch.complex64, (ny, nx)), _stream()))
+    return psi
+
+
+def wasabi_idwt(psi: torch.Tensor, levels: int, u: torch.Tensor | None = None) -> torch.Tensor:
+    ny, nx = psi.shape
+    if u is None:
+        u = torch.empty((ny, nx), dtype=torch.complex64, device=psi.device)
+    if u.dtype != torch.complex64 or u.dim() != 2 or u.shape[0] != ny or u.shape[1] < nx or u.stride(1) != 1:
+        raise ValueError("u must be complex64 (ny, >=nx) with unit column stride")
+    _check(load().wasabi_idwt(_dev(psi, "psi", torch.complex64), nx, ny, levels,
+                              ctypes.c_void_p(u.data_ptr()), u.stride(0), _stream()))
+    return u
+
+
+def _out_window(u, nx, ny, device):
+    if u is None:
+        u = torch.empty((ny, nx), dtype=torch.complex64, device=device)
+    if u.dtype != torch.complex64 or u.dim() != 2 or u.shape[0] != ny or u.shape[1] < nx or u.stride(1) != 1:
+        raise ValueError("u must be complex64 (ny, >=nx) with unit column stride")
+    return u
+
+
+def wasabi_hologram(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, ny: int, sub: int = 0,
+                    u: torch.Tensor | None = None) -> torch.Tensor:
+    n = q.shape[0]
+    u = _out_window(u, nx, ny, q.device)
+    _check(load().wasabi_hologram(lut.handle, _dev(q, "points", torch.int32, (n, 4)), n, ox, oy,
+                                  nx, ny, sub, ctypes.c_void_p(u.data_ptr()), u.stride(0), _stream()))
+    return u
+
+
+def wasabi_hologram_fused(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, ny: int,
+                          u: torch.Tensor | None = None) -> torch.Tensor:
+    n = q.shape[0]
+    u = _out_window(u, nx, ny, q.device)
+    _check(load().wasabi_hologram_fused(lut.handle, _dev(q, "points", torch.int32, (n, 4)), n, ox,
+                                        oy, nx, ny, ctypes.c_void_p(u.data_ptr()), u.stride(0),
+                                        _stream()))
+    return u

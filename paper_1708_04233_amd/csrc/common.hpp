@@ -1,0 +1,103 @@
+// Internal definitions shared by the translation units of libcgh.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "cgh.h"
+
+namespace cgh {
+
+// ---------------------------------------------------------------------------------------------
+// Error reporting: every public entry point returns a cgh_status and leaves a thread-local text.
+// ---------------------------------------------------------------------------------------------
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define CGH_TRY_HIP(call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::cgh::fail(CGH_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+#define CGH_CHECK_LAUNCH(name)                                                                 \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess)                                                                  \
+            return ::cgh::fail(CGH_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+// Stream-ordered scratch: allocated from the device's default pool on `stream` and returned to
+// it on the same stream when the guard goes out of scope.
+class Scratch {
+  public:
+    explicit Scratch(hipStream_t s) : stream_(s) {}
+    ~Scratch();
+    // Returns CGH_OK or CGH_ENOMEM/CGH_EHIP; *p receives device memory of `bytes` bytes.
+    int alloc(void **p, size_t bytes);
+
+  private:
+    hipStream_t stream_;
+    std::vector<void *> ptrs_;
+};
+
+// Keeps the default pool's memory cached between calls (release threshold = unlimited).
+int prepare_pool();
+
+// ---------------------------------------------------------------------------------------------
+// Coefficient LUT, device layout.
+//
+// Plane d's W x W table is cut into nb x nb Haar blocks of B x B pixels (B = 2^L).  Because the
+// Haar transform of an aligned B x B block involves only that block, each block's coefficients
+// are stored with the block: in-block position "code" = ir * B + ic of the block's own L-level
+// Mallat layout.  The kept entries of a plane are ordered by (block row, block column, code) and
+// carry a 16-bit key = block_column * BS(L) + code, where BS(L) is the (padded) block stride of
+// the on-chip tile buffer used by the superposition kernels.  For an entry of block row br,
+// the tile-buffer address is therefore  row_base(br) + key  with one uniform row_base per row.
+// blk_off[d] holds nb*nb + 1 offsets: entries of block (br, bc) are [blk_off[br*nb+bc],
+// blk_off[br*nb+bc+1]) relative to the plane's first entry.
+// ---------------------------------------------------------------------------------------------
+__host__ __device__ constexpr int block_stride(int L)
+{
+    return (1 << (2 * L)) + ((1 << L) <= 16 ? (1 << L) : 0);
+}
+
+struct DepthDesc {
+    int32_t W;            // table side
+    int32_t nb;           // W / B
+    int32_t br0, br1;     // block rows holding kept entries: [br0, br1)
+    int32_t bc0, bc1;     // block columns holding kept entries: [bc0, bc1)
+    int64_t entry_base;   // first entry of the plane in values/keys
+    int64_t blkoff_base;  // first element of the plane's blk_off array
+};
+
+}  // namespace cgh
+
+struct wasabi_lut {
+    wasabi_lut_params prm;
+    int device;
+    int L, B;
+    std::vector<double> z, R;
+    std::vector<int32_t> W;
+    std::vector<int64_t> Nr;
+    std::vector<int64_t> entry_off;   // n_depth + 1
+    std::vector<cgh::DepthDesc> desc_host;
+    int64_t total_entries;
+    int32_t max_span_px;              // largest occupied extent of any plane, pixels
+    cgh::DepthDesc *desc;             // device, n_depth
+    int32_t *blk_off;                 // device
+    void *values;                     // device: float2 (F32) or uint32 packed pair (F16, BF16)
+    uint16_t *keys;                   // device
+    size_t device_bytes;
+};
+
+namespace cgh {
+// Geometry of the planes (Sec. 2, step 1); fills z, R, W, Nr of `lut`.  Returns CGH_OK or CGH_EINVAL.
+int lut_geometry(wasabi_lut *lut);
+int validate_params(const wasabi_lut_params *prm);
+}  // namespace cgh

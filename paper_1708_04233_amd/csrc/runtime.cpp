@@ -1,0 +1,122 @@
+// Error state, stream-ordered scratch and plane geometry of libcgh.so.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace cgh {
+
+static thread_local char g_msg[1024] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_msg[0] = '\0'; }
+
+Scratch::~Scratch()
+{
+    for (void *p : ptrs_) (void)hipFreeAsync(p, stream_);
+}
+
+int Scratch::alloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync(p, bytes, stream_);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        return fail(CGH_ENOMEM, "scratch allocation of %zu bytes failed", bytes);
+    }
+    if (e != hipSuccess) return fail(CGH_EHIP, "hipMallocAsync: %s", hipGetErrorString(e));
+    ptrs_.push_back(*p);
+    return CGH_OK;
+}
+
+int prepare_pool()
+{
+    static std::mutex mu;
+    static std::vector<int> done;
+    int dev = 0;
+    CGH_TRY_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    for (int d : done)
+        if (d == dev) return CGH_OK;
+    hipMemPool_t pool;
+    CGH_TRY_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t thr = UINT64_MAX;
+    CGH_TRY_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    done.push_back(dev);
+    return CGH_OK;
+}
+
+int validate_params(const wasabi_lut_params *prm)
+{
+    if (!prm) return fail(CGH_EINVAL, "params is NULL");
+    if (!(prm->pitch > 0) || !(prm->wavelength > 0) || !(prm->wavelength < 2 * prm->pitch))
+        return fail(CGH_EINVAL, "need 0 < wavelength < 2 * pitch");
+    if (!(prm->z_min > 0) || !(prm->z_max > prm->z_min) || !std::isfinite(prm->z_max))
+        return fail(CGH_EINVAL, "need 0 < z_min < z_max");
+    if (prm->n_depth < 1 || prm->n_depth > 65536) return fail(CGH_EINVAL, "n_depth out of range");
+    if (prm->levels < 1 || prm->levels > 6) return fail(CGH_EINVAL, "levels must be 1..6");
+    if (prm->value_dtype < CGH_F32 || prm->value_dtype > CGH_BF16)
+        return fail(CGH_EINVAL, "unknown value_dtype");
+    if (!(prm->gamma > 0) || !std::isfinite(prm->gamma)) return fail(CGH_EINVAL, "gamma must be > 0");
+    return CGH_OK;
+}
+
+// Sec. 2, step 1: planes at the centres of n_depth equal depth cells; PSF radius from the
+// largest diffraction angle of the pitch (sin theta = lambda / 2p); table side W_d the smallest
+// multiple of 2^(L+1) holding the disk (so the table centre is on the 2^L grid); N_r = gamma pi R^2.
+int lut_geometry(wasabi_lut *lut)
+{
+    const wasabi_lut_params &p = lut->prm;
+    const int n = p.n_depth;
+    const double sin_t = p.wavelength / (2.0 * p.pitch);
+    const double tan_t = sin_t / std::sqrt(1.0 - sin_t * sin_t);
+    const double dz = (p.z_max - p.z_min) / (double)n;
+    const int q = 1 << (p.levels + 1);
+    const int B = 1 << p.levels;
+    const int key_room = 65536 / block_stride(p.levels);  // blocks per row that keys can address
+    lut->z.resize(n);
+    lut->R.resize(n);
+    lut->W.resize(n);
+    lut->Nr.resize(n);
+    for (int d = 0; d < n; d++) {
+        const double z = p.z_min + ((double)d + 0.5) * dz;
+        const double R = z * tan_t / p.pitch;
+        if (!(R < 1e6)) return fail(CGH_EINVAL, "plane %d: PSF radius too large", d);
+        const int64_t need = 2 * (int64_t)std::floor(R) + 2;
+        const int64_t W = ((need + q - 1) / q) * q;
+        if (W > p.max_window)
+            return fail(CGH_EINVAL, "plane %d needs a %lld-pixel table > max_window %d", d,
+                        (long long)W, p.max_window);
+        if (W / B > key_room)
+            return fail(CGH_EINVAL, "plane %d: table side %lld too large for L=%d", d,
+                        (long long)W, p.levels);
+        const int64_t all = W * W;
+        int64_t nr;
+        if (p.gamma >= 1.0) {
+            nr = all;
+        } else {
+            nr = (int64_t)std::ceil(p.gamma * M_PI * R * R);
+            if (nr < 1) nr = 1;
+            if (nr > all) nr = all;
+        }
+        lut->z[d] = z;
+        lut->R[d] = R;
+        lut->W[d] = (int32_t)W;
+        lut->Nr[d] = nr;
+    }
+    return CGH_OK;
+}
+
+}  // namespace cgh
+
+extern "C" const char *cgh_last_error(void) { return cgh::g_msg; }

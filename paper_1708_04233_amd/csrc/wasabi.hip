@@ -1,0 +1,603 @@
+// Wavelet-domain superposition (Eq.(2)), inverse Haar transform (Sec. 2, step 3) and the
+// sub-hologram procedure (Sec. 2, large-scale steps 2-4) for gfx950.
+//
+// Tiles.  The window is cut into 64 x 64 pixel tiles (ragged at the right and bottom edges).  With
+// points and window origins on the 2^L grid, every coefficient a point contributes belongs to one
+// aligned 2^L x 2^L Haar block of the window, so a tile's coefficients are exactly the
+// coefficients of its own blocks.  One workgroup owns one tile and keeps its coefficients in LDS,
+// block by block (each block in its own L-level Mallat layout, padded block stride BS(L)).
+//
+// Binning.  bin_count / scan / bin_fill build, for every tile, the list of points whose
+// occupied table area overlaps it (global atomics only on the per-tile counters).
+//
+// Superposition.  For a (tile, point) pair the table blocks that fall in the tile form a
+// rectangle; its entries are one contiguous LUT range per block row.  A wave walks the
+// concatenated ranges 64 entries at a time and adds a_j * c into LDS with ds_add_f32 at
+// row_base(block row) + key, so no global atomics touch the wavelet field.
+//
+// Output.  MODE_PSI scatters the tile's coefficients into the Mallat layout of the window;
+// MODE_FUSED inverts each block in LDS and writes pixels, so the wavelet field never reaches HBM.
+// idwt_kernel gathers a tile from a Mallat-layout field, inverts it in LDS and writes pixels.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace cgh {
+namespace {
+
+constexpr int kT = 64;  // tile side, pixels
+constexpr int kThreads = 256;
+constexpr int MODE_PSI = 0, MODE_FUSED = 1;
+
+struct TileGeom {
+    int64_t ox, oy;    // window origin, global pixels
+    int32_t nx, ny;    // window size
+    int32_t ntx, nty;  // tiles per row / column
+};
+
+// Tiles touched by the occupied part of point p's table; false if none.
+__device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, int n_depth, int L,
+                                 const TileGeom &g, int &ty0, int &ty1, int &tx0, int &tx1)
+{
+    if (p.depth < 0 || p.depth >= n_depth) return false;
+    const DepthDesc d = desc[p.depth];
+    if (d.br1 <= d.br0) return false;
+    const int64_t B = 1 << L;
+    const int64_t xg = (int64_t)(p.x >> L) * B, yg = (int64_t)(p.y >> L) * B;  // floor to grid
+    const int64_t r_org = yg - d.W / 2 - g.oy, c_org = xg - d.W / 2 - g.ox;
+    const int64_t r0 = r_org + d.br0 * B, r1 = r_org + d.br1 * B;
+    const int64_t c0 = c_org + d.bc0 * B, c1 = c_org + d.bc1 * B;
+    if (r1 <= 0 || c1 <= 0 || r0 >= g.ny || c0 >= g.nx) return false;
+    ty0 = (int)(max(r0, (int64_t)0) / kT);
+    ty1 = (int)((min(r1, (int64_t)g.ny) - 1) / kT) + 1;
+    tx0 = (int)(max(c0, (int64_t)0) / kT);
+    tx1 = (int)((min(c1, (int64_t)g.nx) - 1) / kT) + 1;
+    return true;
+}
+
+__global__ void bin_count_kernel(const wasabi_point *pts, int64_t n, const DepthDesc *desc,
+                                 int n_depth, int L, TileGeom g, int32_t *counts)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int ty0, ty1, tx0, tx1;
+    if (!footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) return;
+    for (int ty = ty0; ty < ty1; ++ty)
+        for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&counts[(int64_t)ty * g.ntx + tx], 1);
+}
+
+__global__ void bin_fill_kernel(const wasabi_point *pts, int64_t n, const DepthDesc *desc,
+                                int n_depth, int L, TileGeom g, unsigned long long *cursor,
+                                int32_t *list)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int ty0, ty1, tx0, tx1;
+    if (!footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) return;
+    for (int ty = ty0; ty < ty1; ++ty)
+        for (int tx = tx0; tx < tx1; ++tx) {
+            const unsigned long long slot = atomicAdd(&cursor[(int64_t)ty * g.ntx + tx], 1ull);
+            list[slot] = (int32_t)j;
+        }
+}
+
+// ---- exclusive scan of int32 counts into int64 offsets (n + 1 values) ----------------------
+__device__ inline int64_t block_incl_scan(int64_t v, int64_t *wave_sums, int64_t &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) wave_sums[wave] = v;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        const int64_t s = wave_sums[w];
+        off += (w < wave) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return v + off;
+}
+
+__global__ __launch_bounds__(1024) void scan_local_kernel(const int32_t *counts, int64_t n,
+                                                          int64_t *off, int64_t *bsum)
+{
+    __shared__ int64_t ws[16];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int64_t v = i < n ? counts[i] : 0;
+    int64_t tot;
+    const int64_t incl = block_incl_scan(v, ws, tot);
+    if (i < n) off[i] = incl - v;
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t *bsum, int64_t nb, int64_t *total_out)
+{
+    __shared__ int64_t ws[16];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < nb ? bsum[i] : 0;
+        int64_t tot;
+        const int64_t incl = block_incl_scan(v, ws, tot);
+        if (i < nb) bsum[i] = carry + incl - v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void scan_add_kernel(int64_t *off, int64_t n, const int64_t *bsum)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) off[i] += bsum[i / 1024];
+}
+
+// ---- tile kernels ---------------------------------------------------------------------------
+struct TileArgs {
+    const DepthDesc *desc;
+    const int32_t *blk_off;
+    const void *values;
+    const uint16_t *keys;
+    const wasabi_point *pts;
+    const int64_t *tile_off;
+    const int32_t *tile_pts;
+    TileGeom g;
+    const float2 *in;  // idwt: Mallat-layout field of the window (contiguous, row stride nx)
+    float2 *out;       // MODE_PSI: Mallat field (row stride nx); otherwise pixels (row stride ld)
+    int64_t ld;
+};
+
+template <int L>
+struct TileShape {
+    static constexpr int B = 1 << L;
+    static constexpr int TB = kT / B;             // blocks per tile side
+    static constexpr int BS = block_stride(L);    // LDS floats per block
+    static constexpr int ROW = TB * BS;           // LDS floats per block row
+    static constexpr int N = TB * ROW;            // LDS floats per plane (re or im)
+};
+
+template <int VT>
+__device__ inline float2 load_value(const void *values, int64_t i)
+{
+    if (VT == CGH_F32) return ((const float2 *)values)[i];
+    const uint32_t w = ((const uint32_t *)values)[i];
+    if (VT == CGH_F16) {
+        _Float16 lo, hi;
+        const uint16_t l16 = (uint16_t)(w & 0xffff), h16 = (uint16_t)(w >> 16);
+        __builtin_memcpy(&lo, &l16, 2);
+        __builtin_memcpy(&hi, &h16, 2);
+        return make_float2((float)lo, (float)hi);
+    }
+    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
+// Moves the tile's coefficients between LDS and the window's Mallat layout (rows of nx).
+template <int L, bool TO_LDS>
+__device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, const TileGeom &g,
+                                      int ty, int tx, int th, int tw)
+{
+    using S = TileShape<L>;
+    const int64_t nx = g.nx;
+#pragma unroll
+    for (int l = 1; l <= L; ++l) {
+        const int wf = kT >> l;          // band extent of a full tile at level l
+        const int h = S::B >> l;         // band extent inside one block
+        const int hb = th >> l, wb = tw >> l;
+        for (int band = 1; band <= 3; ++band) {
+            const int64_t row0 = (band & 2) ? (g.ny >> l) : 0, col0 = (band & 1) ? (g.nx >> l) : 0;
+            for (int i = threadIdx.x; i < wf * wf; i += kThreads) {
+                const int m = i / wf, n = i % wf;
+                if (m >= hb || n >= wb) continue;
+                const int code = (((band & 2) ? h : 0) + (m & (h - 1))) * S::B + ((band & 1) ? h : 0) + (n & (h - 1));
+                const int at = (m / h) * S::ROW + (n / h) * S::BS + code;
+                float2 *f = field + (row0 + (int64_t)ty * wf + m) * nx + col0 + (int64_t)tx * wf + n;
+                if (TO_LDS) {
+                    const float2 v = *f;
+                    sre[at] = v.x;
+                    sim[at] = v.y;
+                } else {
+                    *f = make_float2(sre[at], sim[at]);
+                }
+            }
+        }
+    }
+    {
+        const int wf = kT >> L;
+        const int hb = th >> L, wb = tw >> L;
+        for (int i = threadIdx.x; i < wf * wf; i += kThreads) {
+            const int m = i / wf, n = i % wf;
+            if (m >= hb || n >= wb) continue;
+            const int at = m * S::ROW + n * S::BS;
+            float2 *f = field + ((int64_t)ty * wf + m) * nx + (int64_t)tx * wf + n;
+            if (TO_LDS) {
+                const float2 v = *f;
+                sre[at] = v.x;
+                sim[at] = v.y;
+            } else {
+                *f = make_float2(sre[at], sim[at]);
+            }
+        }
+    }
+}
+
+// In-LDS inverse Haar of every block of the tile, then the pixels go to out (row stride ld).
+template <int L>
+__device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *out, int64_t ld,
+                                              int ty, int tx, int th, int tw)
+{
+    using S = TileShape<L>;
+    constexpr int MAXQ = (kT * kT / 4 + kThreads - 1) / kThreads;
+#pragma unroll
+    for (int l = L; l >= 1; --l) {
+        const int h = S::B >> l;           // S^(l) extent inside a block
+        const int per = h * h;
+        const int nq = (kT >> l) * (kT >> l);
+        float r[MAXQ][4], im[MAXQ][4];
+        int base[MAXQ], mm[MAXQ], nn[MAXQ];
+#pragma unroll
+        for (int k = 0; k < MAXQ; ++k) {
+            const int qi = threadIdx.x + kThreads * k;
+            if (qi < nq) {
+                const int blk = qi / per, w = qi % per;
+                const int m = w / h, n = w % h;
+                const int b = (blk / S::TB) * S::ROW + (blk % S::TB) * S::BS;
+                base[k] = b;
+                mm[k] = m;
+                nn[k] = n;
+                const int s0 = b + m * S::B + n, s1 = s0 + h, s2 = s0 + h * S::B, s3 = s2 + h;
+                r[k][0] = sre[s0]; r[k][1] = sre[s1]; r[k][2] = sre[s2]; r[k][3] = sre[s3];
+                im[k][0] = sim[s0]; im[k][1] = sim[s1]; im[k][2] = sim[s2]; im[k][3] = sim[s3];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXQ; ++k) {
+            const int qi = threadIdx.x + kThreads * k;
+            if (qi < nq) {
+                const int a00 = base[k] + (2 * mm[k]) * S::B + 2 * nn[k];
+                const int a10 = a00 + S::B;
+                const float Sr = r[k][0], Hr = r[k][1], Vr = r[k][2], Dr = r[k][3];
+                const float Si = im[k][0], Hi = im[k][1], Vi = im[k][2], Di = im[k][3];
+                sre[a00] = (Sr + Hr + Vr + Dr) * 0.5f;
+                sre[a00 + 1] = (Sr - Hr + Vr - Dr) * 0.5f;
+                sre[a10] = (Sr + Hr - Vr - Dr) * 0.5f;
+                sre[a10 + 1] = (Sr - Hr - Vr + Dr) * 0.5f;
+                sim[a00] = (Si + Hi + Vi + Di) * 0.5f;
+                sim[a00 + 1] = (Si - Hi + Vi - Di) * 0.5f;
+                sim[a10] = (Si + Hi - Vi - Di) * 0.5f;
+                sim[a10 + 1] = (Si - Hi - Vi + Di) * 0.5f;
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < kT * kT; i += kThreads) {
+        const int rr = i / kT, cc = i % kT;
+        if (rr >= th || cc >= tw) continue;
+        const int at = (rr >> L) * S::ROW + (cc >> L) * S::BS + (rr & (S::B - 1)) * S::B + (cc & (S::B - 1));
+        out[((int64_t)ty * kT + rr) * ld + (int64_t)tx * kT + cc] = make_float2(sre[at], sim[at]);
+    }
+}
+
+template <int L, int VT, int MODE>
+__global__ __launch_bounds__(kThreads) void tile_kernel(TileArgs a)
+{
+    using S = TileShape<L>;
+    __shared__ float sre[S::N];
+    __shared__ float sim[S::N];
+    const int tile = blockIdx.x;
+    const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
+    const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
+    const int tbh = th >> L, tbw = tw >> L;
+    for (int i = threadIdx.x; i < S::N; i += kThreads) {
+        sre[i] = 0.0f;
+        sim[i] = 0.0f;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
+    const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
+    for (int64_t p = p0 + wave; p < p1; p += kThreads / 64) {
+        const wasabi_point pt = a.pts[a.tile_pts[p]];
+        const DepthDesc dd = a.desc[pt.depth];
+        const int64_t xg = (int64_t)(pt.x >> L) << L, yg = (int64_t)(pt.y >> L) << L;
+        const int obr = (int)((yg - dd.W / 2 - gy0) >> L);  // table block (0,0) in tile blocks
+        const int obc = (int)((xg - dd.W / 2 - gx0) >> L);
+        const int br0 = max(dd.br0, -obr), br1 = min(dd.br1, tbh - obr);
+        const int bc0 = max(dd.bc0, -obc), bc1 = min(dd.bc1, tbw - obc);
+        if (br0 >= br1 || bc0 >= bc1) continue;
+        const int nrows = br1 - br0;
+        int rstart = 0, rcount = 0;
+        if (lane < nrows) {
+            const int32_t *bo = a.blk_off + dd.blkoff_base + (int64_t)(br0 + lane) * dd.nb;
+            rstart = bo[bc0];
+            rcount = bo[bc1] - rstart;
+        }
+        int incl = rcount;
+        for (int o = 1; o < S::TB; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        const int total = __builtin_amdgcn_readlane(incl, S::TB - 1);
+        if (total == 0) continue;
+        const float amp = pt.a;
+        const int64_t ebase = dd.entry_base;
+        const uint16_t *keys = a.keys + ebase;
+        const int dst0 = (br0 + obr) * S::ROW + obc * S::BS;
+        for (int base = 0; base < total; base += 64) {
+            const int e = base + lane;
+            int src = 0, dst = 0;
+            for (int r = 0; r < nrows; ++r) {
+                const int hi = __builtin_amdgcn_readlane(incl, r);
+                const int lo = hi - __builtin_amdgcn_readlane(rcount, r);
+                if (lo < base + 64 && hi > base && e >= lo) {
+                    src = __builtin_amdgcn_readlane(rstart, r) - lo;
+                    dst = dst0 + r * S::ROW;
+                }
+            }
+            if (e < total) {
+                const int li = src + e;
+                const float2 v = load_value<VT>(a.values, ebase + li);
+                const int at = dst + keys[li];
+                atomicAdd(&sre[at], amp * v.x);
+                atomicAdd(&sim[at], amp * v.y);
+            }
+        }
+    }
+    __syncthreads();
+
+    if (MODE == MODE_PSI) {
+        tile_mallat_io<L, false>(sre, sim, a.out, a.g, ty, tx, th, tw);
+    } else {
+        tile_inverse_and_store<L>(sre, sim, a.out, a.ld, ty, tx, th, tw);
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(kThreads) void idwt_kernel(TileArgs a)
+{
+    using S = TileShape<L>;
+    __shared__ float sre[S::N];
+    __shared__ float sim[S::N];
+    const int tile = blockIdx.x;
+    const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
+    const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
+    tile_mallat_io<L, true>(sre, sim, const_cast<float2 *>(a.in), a.g, ty, tx, th, tw);
+    __syncthreads();
+    tile_inverse_and_store<L>(sre, sim, a.out, a.ld, ty, tx, th, tw);
+}
+
+// ---- host side ------------------------------------------------------------------------------
+TileGeom make_geom(int64_t ox, int64_t oy, int32_t nx, int32_t ny)
+{
+    TileGeom g;
+    g.ox = ox;
+    g.oy = oy;
+    g.nx = nx;
+    g.ny = ny;
+    g.ntx = (nx + kT - 1) / kT;
+    g.nty = (ny + kT - 1) / kT;
+    return g;
+}
+
+int check_window(int L, int64_t ox, int64_t oy, int32_t nx, int32_t ny)
+{
+    const int B = 1 << L;
+    if (nx < B || ny < B || nx % B || ny % B)
+        return fail(CGH_EINVAL, "window %d x %d must be a positive multiple of 2^L = %d", nx, ny, B);
+    if (ox % B || oy % B) return fail(CGH_EINVAL, "window origin must be a multiple of 2^L = %d", B);
+    const int64_t lim = INT64_C(1) << 40;
+    if (ox < -lim || oy < -lim || ox > lim || oy > lim) return fail(CGH_EINVAL, "window origin out of range");
+    return CGH_OK;
+}
+
+// Build the per-tile point lists; results live in `sc`.
+int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,
+               Scratch &sc, hipStream_t s, int64_t **tile_off_out, int32_t **tile_pts_out)
+{
+    const int64_t ntiles = (int64_t)g.ntx * g.nty;
+    const int64_t per_side = (lut->max_span_px + kT - 1) / kT + 1;
+    const int64_t per_point = std::min<int64_t>(per_side * per_side, ntiles);
+    const int64_t bound = std::max<int64_t>(n * per_point, 1);
+    const int64_t nblk = (ntiles + 1023) / 1024;
+    int32_t *counts;
+    int64_t *off, *bsum;
+    unsigned long long *cursor;
+    int32_t *list;
+    int rc;
+    if ((rc = sc.alloc((void **)&counts, sizeof(int32_t) * ntiles))) return rc;
+    if ((rc = sc.alloc((void **)&off, sizeof(int64_t) * (ntiles + 1)))) return rc;
+    if ((rc = sc.alloc((void **)&bsum, sizeof(int64_t) * nblk))) return rc;
+    if ((rc = sc.alloc((void **)&cursor, sizeof(unsigned long long) * ntiles))) return rc;
+    if ((rc = sc.alloc((void **)&list, sizeof(int32_t) * bound))) return rc;
+    CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
+    const int nd = lut->prm.n_depth, L = lut->L;
+    const unsigned pblocks = (unsigned)((n + 255) / 256);
+    if (n > 0) {
+        hipLaunchKernelGGL(bin_count_kernel, dim3(pblocks), dim3(256), 0, s, pts, n, lut->desc, nd, L, g, counts);
+        CGH_CHECK_LAUNCH("bin_count_kernel");
+    }
+    hipLaunchKernelGGL(scan_local_kernel, dim3((unsigned)nblk), dim3(1024), 0, s, counts, ntiles, off, bsum);
+    CGH_CHECK_LAUNCH("scan_local_kernel");
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nblk, off + ntiles);
+    CGH_CHECK_LAUNCH("scan_sums_kernel");
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, off, ntiles, bsum);
+    CGH_CHECK_LAUNCH("scan_add_kernel");
+    if (n > 0) {
+        CGH_TRY_HIP(hipMemcpyAsync(cursor, off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(bin_fill_kernel, dim3(pblocks), dim3(256), 0, s, pts, n, lut->desc, nd, L, g, cursor, list);
+        CGH_CHECK_LAUNCH("bin_fill_kernel");
+    }
+    *tile_off_out = off;
+    *tile_pts_out = list;
+    return CGH_OK;
+}
+
+template <int L, int MODE>
+void launch_tile_l(int vt, const TileArgs &a, unsigned grid, hipStream_t s)
+{
+    if (vt == CGH_F32) hipLaunchKernelGGL((tile_kernel<L, CGH_F32, MODE>), dim3(grid), dim3(kThreads), 0, s, a);
+    else if (vt == CGH_F16) hipLaunchKernelGGL((tile_kernel<L, CGH_F16, MODE>), dim3(grid), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((tile_kernel<L, CGH_BF16, MODE>), dim3(grid), dim3(kThreads), 0, s, a);
+}
+
+template <int MODE>
+int launch_tile(int L, int vt, const TileArgs &a, hipStream_t s)
+{
+    const int64_t ntiles = (int64_t)a.g.ntx * a.g.nty;
+    if (ntiles > INT32_MAX) return fail(CGH_EINVAL, "too many tiles");
+    const unsigned grid = (unsigned)ntiles;
+    switch (L) {
+    case 1: launch_tile_l<1, MODE>(vt, a, grid, s); break;
+    case 2: launch_tile_l<2, MODE>(vt, a, grid, s); break;
+    case 3: launch_tile_l<3, MODE>(vt, a, grid, s); break;
+    case 4: launch_tile_l<4, MODE>(vt, a, grid, s); break;
+    case 5: launch_tile_l<5, MODE>(vt, a, grid, s); break;
+    default: launch_tile_l<6, MODE>(vt, a, grid, s); break;
+    }
+    CGH_CHECK_LAUNCH("tile_kernel");
+    return CGH_OK;
+}
+
+TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t *tile_off,
+                   const int32_t *tile_pts, const TileGeom &g, float2 *out, int64_t ld)
+{
+    TileArgs a;
+    a.desc = lut ? lut->desc : nullptr;
+    a.blk_off = lut ? lut->blk_off : nullptr;
+    a.values = lut ? lut->values : nullptr;
+    a.keys = lut ? lut->keys : nullptr;
+    a.pts = pts;
+    a.tile_off = tile_off;
+    a.tile_pts = tile_pts;
+    a.g = g;
+    a.in = nullptr;
+    a.out = out;
+    a.ld = ld;
+    return a;
+}
+
+int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox,
+                   int64_t oy, int32_t nx, int32_t ny, void *out, int64_t ld, int mode,
+                   hipStream_t s)
+{
+    int rc = prepare_pool();
+    if (rc) return rc;
+    const TileGeom g = make_geom(ox, oy, nx, ny);
+    Scratch sc(s);
+    int64_t *tile_off;
+    int32_t *tile_pts;
+    rc = bin_points(lut, pts, n, g, sc, s, &tile_off, &tile_pts);
+    if (rc) return rc;
+    const TileArgs a = make_args(lut, pts, tile_off, tile_pts, g, (float2 *)out, ld);
+    if (mode == MODE_PSI) return launch_tile<MODE_PSI>(lut->L, lut->prm.value_dtype, a, s);
+    return launch_tile<MODE_FUSED>(lut->L, lut->prm.value_dtype, a, s);
+}
+
+int check_common(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox, int64_t oy,
+                 int32_t nx, int32_t ny, const void *out)
+{
+    if (!lut) return fail(CGH_EINVAL, "lut is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(CGH_EINVAL, "n out of range");
+    if (n > 0 && !pts) return fail(CGH_EINVAL, "pts is NULL");
+    if (!out) return fail(CGH_EINVAL, "output is NULL");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != lut->device) return fail(CGH_EINVAL, "LUT lives on device %d, current is %d", lut->device, dev);
+    return check_window(lut->L, ox, oy, nx, ny);
+}
+
+int idwt_impl(const void *psi, int32_t nx, int32_t ny, int32_t levels, void *u, int64_t ld,
+              hipStream_t s)
+{
+    const TileGeom g = make_geom(0, 0, nx, ny);
+    TileArgs a = make_args(nullptr, nullptr, nullptr, nullptr, g, (float2 *)u, ld);
+    a.in = (const float2 *)psi;
+    const int64_t ntiles = (int64_t)g.ntx * g.nty;
+    if (ntiles > INT32_MAX) return fail(CGH_EINVAL, "too many tiles");
+    const dim3 grid((unsigned)ntiles);
+    switch (levels) {
+    case 1: hipLaunchKernelGGL(idwt_kernel<1>, grid, dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(idwt_kernel<2>, grid, dim3(kThreads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(idwt_kernel<3>, grid, dim3(kThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(idwt_kernel<4>, grid, dim3(kThreads), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(idwt_kernel<5>, grid, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL(idwt_kernel<6>, grid, dim3(kThreads), 0, s, a); break;
+    }
+    CGH_CHECK_LAUNCH("idwt_kernel");
+    return CGH_OK;
+}
+
+}  // namespace
+}  // namespace cgh
+
+extern "C" int wasabi_superpose(const wasabi_lut *lut, const wasabi_point *pts, int64_t n,
+                                int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *psi,
+                                void *stream)
+{
+    using namespace cgh;
+    int rc = check_common(lut, pts, n, ox, oy, nx, ny, psi);
+    if (rc) return rc;
+    return superpose_impl(lut, pts, n, ox, oy, nx, ny, psi, nx, MODE_PSI, (hipStream_t)stream);
+}
+
+extern "C" int wasabi_idwt(const void *psi, int32_t nx, int32_t ny, int32_t levels, void *u,
+                           int64_t ld_u, void *stream)
+{
+    using namespace cgh;
+    if (!psi || !u) return fail(CGH_EINVAL, "NULL pointer");
+    if (levels < 1 || levels > 6) return fail(CGH_EINVAL, "levels must be 1..6");
+    int rc = check_window(levels, 0, 0, nx, ny);
+    if (rc) return rc;
+    if (ld_u < nx) return fail(CGH_EINVAL, "ld_u < nx");
+    if (psi == u) return fail(CGH_EINVAL, "u must not overlap psi");
+    return idwt_impl(psi, nx, ny, levels, u, ld_u, (hipStream_t)stream);
+}
+
+extern "C" int wasabi_hologram(const wasabi_lut *lut, const wasabi_point *pts, int64_t n,
+                               int64_t ox, int64_t oy, int32_t nx, int32_t ny, int32_t sub,
+                               void *u, int64_t ld_u, void *stream)
+{
+    using namespace cgh;
+    int rc = check_common(lut, pts, n, ox, oy, nx, ny, u);
+    if (rc) return rc;
+    if (ld_u < nx) return fail(CGH_EINVAL, "ld_u < nx");
+    const int B = lut->B;
+    if (sub < 0 || sub % B) return fail(CGH_EINVAL, "sub must be 0 or a positive multiple of 2^L");
+    if (sub == 0) sub = std::max(nx, ny);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = prepare_pool())) return rc;
+    const int32_t sx = std::min(sub, nx), sy = std::min(sub, ny);
+    Scratch sc(s);
+    float2 *psi;
+    if ((rc = sc.alloc((void **)&psi, sizeof(float2) * (size_t)sx * sy))) return rc;
+    // Sec. 2, large-scale procedure: for every sub-hologram (s, t), shift the points
+    // (x'_j = x_j - s N_h), superpose in the wavelet domain, invert into the hologram.
+    for (int64_t t0 = 0; t0 < ny; t0 += sub) {
+        for (int64_t s0 = 0; s0 < nx; s0 += sub) {
+            const int32_t wx = (int32_t)std::min<int64_t>(sub, nx - s0);
+            const int32_t wy = (int32_t)std::min<int64_t>(sub, ny - t0);
+            rc = superpose_impl(lut, pts, n, ox + s0, oy + t0, wx, wy, psi, wx, MODE_PSI, s);
+            if (rc) return rc;
+            float2 *uw = (float2 *)u + t0 * ld_u + s0;
+            rc = idwt_impl(psi, wx, wy, lut->L, uw, ld_u, s);
+            if (rc) return rc;
+        }
+    }
+    return CGH_OK;
+}
+
+extern "C" int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts, int64_t n,
+                                     int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *u,
+                                     int64_t ld_u, void *stream)
+{
+    using namespace cgh;
+    int rc = check_common(lut, pts, n, ox, oy, nx, ny, u);
+    if (rc) return rc;
+    if (ld_u < nx) return fail(CGH_EINVAL, "ld_u < nx");
+    return superpose_impl(lut, pts, n, ox, oy, nx, ny, u, ld_u, MODE_FUSED, (hipStream_t)stream);
+}

@@ -1,0 +1,37 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function that
+include/cgh.h declares, and rejects bad arguments before touching the device."""
+import ctypes
+
+import pytest
+
+import paper_1708_04233_amd as cgh
+
+
+def test_exports_every_declared_function():
+    lib = cgh.load()
+    names = cgh.header_functions()
+    assert "cgh_direct" in names and "wasabi_superpose" in names and len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_argument_validation_without_device():
+    lib = cgh.load()
+    out = ctypes.c_void_p(16)
+    # bad sizes, wavelength >= 2 pitch, unknown window / dtype
+    assert lib.cgh_direct(None, 0, 0, 4, 0, 0, 1e-6, 633e-9, 0, 0, out, 4, None) == cgh.CGH_EINVAL
+    assert lib.cgh_direct(None, 0, 4, 4, 0, 0, 1e-6, 2.5e-6, 0, 0, out, 4, None) == cgh.CGH_EINVAL
+    assert lib.cgh_direct(None, 0, 4, 4, 0, 0, 1e-6, 633e-9, 7, 0, out, 4, None) == cgh.CGH_EINVAL
+    assert lib.cgh_direct(None, 0, 4, 4, 0, 0, 1e-6, 633e-9, 0, 9, out, 4, None) == cgh.CGH_EINVAL
+    assert lib.cgh_direct(None, 3, 4, 4, 0, 0, 1e-6, 633e-9, 0, 0, out, 4, None) == cgh.CGH_EINVAL
+    assert b"NULL" in lib.cgh_last_error()
+    h = ctypes.c_void_p()
+    for bad in [dict(levels=0), dict(levels=7), dict(n_depth=0), dict(gamma=0.0),
+                dict(z_min=2e-3), dict(wavelength=3e-6), dict(value_dtype=5),
+                dict(max_window=512)]:
+        prm = cgh.LutParams(**bad).c()
+        assert lib.wasabi_build_lut(ctypes.byref(prm), ctypes.byref(h), None) == cgh.CGH_EINVAL, bad
+        assert not h.value
+    assert lib.wasabi_idwt(out, 12, 16, 3, out, 16, None) == cgh.CGH_EINVAL   # 12 % 8 != 0
+    assert lib.wasabi_idwt(out, 16, 16, 3, out, 16, None) == cgh.CGH_EINVAL   # u aliases psi
+    assert lib.wasabi_superpose(None, None, 0, 0, 0, 16, 16, out, None) == cgh.CGH_EINVAL

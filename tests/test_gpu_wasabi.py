@@ -1,0 +1,167 @@
+"""GPU parity of the wavelet path against the FP64 oracle: quantisation, Eq.(2) superposition,
+inverse Haar transform, the sub-hologram procedure and the fused tile path.
+
+Superposition parity uses the oracle's own LUT imported into the library, so both sides add the
+same coefficients (the oracle takes no input from the GPU).  Tolerance: relative L2 <= 1e-5 for
+the FP32-accumulating GPU path against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1708_04233_amd as cgh
+from workloads import WASABI_2048, grid_points, uniform_points
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _rel(u, ref):
+    ref = np.asarray(ref)
+    return float(np.linalg.norm((np.asarray(u, np.complex128) - ref).ravel()) /
+                 max(np.linalg.norm(ref.ravel()), 1e-300))
+
+
+def _luts(orc, levels, gamma, dtype=0, n_depth=5, z_max=90e-6, max_window=256):
+    kw = dict(z_min=20e-6, z_max=z_max, n_depth=n_depth, levels=levels, gamma=gamma,
+              max_window=max_window, value_dtype=dtype)
+    ref = orc.build_lut(orc.LutParams(**kw))
+    gpu = cgh.wasabi_lut_import(cgh.LutParams(**kw), ref.off, ref.idx, ref.val)
+    return ref, gpu
+
+
+def _points(seed, n, nx, ny, B, x0=0, y0=0, z=(20e-6, 90e-6)):
+    return grid_points(seed, n, nx, ny, B, z[0], z[1], x0=x0, y0=y0)
+
+
+def _q_gpu(gpu_lut, pts):
+    return cgh.wasabi_quantize(gpu_lut, torch.from_numpy(pts).cuda())
+
+
+def test_quantize_matches_oracle(orc):
+    ref, gpu = _luts(orc, 3, 0.2)
+    pts = uniform_points(4, 2000, 400, 300, 10e-6, 100e-6)
+    pts[:, :2] -= 150e-6                      # negative coordinates
+    pts[::97, 2] = np.nan                     # non-finite -> invalid
+    pts[5, 2] = ref.params.z_max              # top plane edge
+    pts[6, 2] = ref.params.z_min
+    q = _q_gpu(gpu, pts).cpu().numpy()
+    o = orc.quantize(pts, ref.params)
+    np.testing.assert_array_equal(q[:, 0], o.x)
+    np.testing.assert_array_equal(q[:, 1], o.y)
+    np.testing.assert_array_equal(q[:, 2], o.d)
+    np.testing.assert_array_equal(q[:, 3].view(np.float32), o.a.astype(np.float32))
+    assert (o.d == -1).sum() > 100 and (o.d >= 0).sum() > 100
+
+
+CASES = [(1, 0.3, 0), (2, 0.2, 0), (3, 0.05, 0), (3, 0.6, 0), (4, 0.3, 0), (5, 0.3, 0),
+         (6, 0.5, 0), (3, 0.3, 1), (3, 0.3, 2)]
+
+
+@pytest.mark.parametrize("levels,gamma,dtype", CASES)
+def test_superpose_matches_oracle(orc, levels, gamma, dtype):
+    ref, gpu = _luts(orc, levels, gamma, dtype)
+    B = 1 << levels
+    # ragged window (not a multiple of the 64-pixel tile unless B = 64), negative origin
+    nx, ny = (200 // B) * B if B < 64 else 192, (136 // B) * B if B < 64 else 128
+    X0, Y0 = -B * 2, B * 3
+    pts = _points(10 + levels, 60, nx + 160, ny + 160, B, x0=X0 - 80, y0=Y0 - 80)
+    q = _q_gpu(gpu, pts)
+    psi = cgh.wasabi_superpose(gpu, q, X0, Y0, nx, ny).cpu().numpy()
+    want = orc.superpose(ref, orc.quantize(pts, ref.params), X0, Y0, nx, ny)
+    assert _rel(psi, want) < TOL
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6])
+def test_idwt_matches_oracle(orc, levels):
+    B = 1 << levels
+    nx, ny = max(B, (200 // B) * B), max(B, (72 // B) * B)
+    rng = np.random.default_rng(levels)
+    psi = (rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))).astype(np.complex64)
+    u = torch.full((ny, nx + 24), 3.0, dtype=torch.complex64, device="cuda")
+    cgh.wasabi_idwt(torch.from_numpy(psi).cuda(), levels, u=u)
+    got = u.cpu().numpy()
+    assert _rel(got[:, :nx], orc.haar_inverse(psi.astype(np.complex128), levels)) < 1e-6
+    assert np.all(got[:, nx:] == 3.0)
+
+
+@pytest.mark.parametrize("levels,sub", [(3, 64), (3, 0), (4, 96), (2, 40)])
+def test_hologram_and_fused_match_oracle(orc, levels, sub):
+    ref, gpu = _luts(orc, levels, 0.25)
+    B = 1 << levels
+    nx, ny, X0, Y0 = (208 // B) * B, (144 // B) * B, -B * 5, -B * 2
+    pts = _points(30 + levels, 80, nx + 160, ny + 160, B, x0=X0 - 80, y0=Y0 - 80)
+    q = _q_gpu(gpu, pts)
+    want = orc.wasabi(ref, orc.quantize(pts, ref.params), X0, Y0, nx, ny)
+    u = torch.full((ny, nx + 8), 5.0, dtype=torch.complex64, device="cuda")
+    cgh.wasabi_hologram(gpu, q, X0, Y0, nx, ny, sub=sub, u=u)
+    got = u.cpu().numpy()
+    assert _rel(got[:, :nx], want) < TOL
+    assert np.all(got[:, nx:] == 5.0)
+    fused = cgh.wasabi_hologram_fused(gpu, q, X0, Y0, nx, ny).cpu().numpy()
+    assert _rel(fused, want) < TOL
+
+
+def test_no_points_and_invalid_points(orc):
+    ref, gpu = _luts(orc, 3, 0.3)
+    q = cgh.points_tensor(0)
+    assert torch.count_nonzero(cgh.wasabi_hologram_fused(gpu, q, 0, 0, 72, 64)).item() == 0
+    assert torch.count_nonzero(cgh.wasabi_superpose(gpu, q, 0, 0, 72, 64)).item() == 0
+    pts = _points(2, 50, 64, 64, 8)
+    pts[:, 2] = 1.0                           # every point beyond z_max -> invalid
+    q = _q_gpu(gpu, pts)
+    assert torch.count_nonzero(cgh.wasabi_hologram(gpu, q, 0, 0, 64, 64)).item() == 0
+
+
+def test_window_argument_checks(orc):
+    ref, gpu = _luts(orc, 3, 0.3)
+    q = cgh.points_tensor(4)
+    for bad in [(4, 0, 64, 64), (0, 0, 60, 64), (0, 0, 64, 0)]:
+        with pytest.raises(cgh.CghError):
+            cgh.wasabi_superpose(gpu, q, *bad, psi=torch.empty((bad[3], bad[2]),
+                                                                  dtype=torch.complex64, device="cuda"))
+    with pytest.raises(cgh.CghError):
+        cgh.wasabi_hologram(gpu, q, 0, 0, 64, 64, sub=12)
+
+
+def test_full_lut_equals_direct_sum_on_gpu(orc):
+    """gamma >= 1 with on-grid points: WASABI equals the circ()-windowed Eq.(1) sum."""
+    kw = dict(z_min=20e-6, z_max=90e-6, n_depth=6, levels=3, gamma=1.0, max_window=256)
+    gpu = cgh.wasabi_build_lut(cgh.LutParams(**kw))
+    pts = _points(8, 200, 320, 256, 8, x0=-32, y0=-32)
+    q = _q_gpu(gpu, pts)
+    u = cgh.wasabi_hologram_fused(gpu, q, 0, 0, 256, 192).cpu().numpy()
+    snapped = orc.snapped_points(orc.quantize(pts, orc.LutParams(**kw)), orc.build_lut(orc.LutParams(**kw)))
+    d = cgh.cgh_direct(torch.from_numpy(snapped).cuda(), 256, 192, window=cgh.CIRC).cpu().numpy()
+    assert _rel(u, d) < TOL
+
+
+def test_own_lut_end_to_end(orc):
+    """GPU-built LUT against the oracle-built LUT: they may differ at near-tied magnitudes."""
+    kw = dict(z_min=20e-6, z_max=90e-6, n_depth=6, levels=3, gamma=0.2, max_window=256)
+    gpu = cgh.wasabi_build_lut(cgh.LutParams(**kw))
+    ref = orc.build_lut(orc.LutParams(**kw))
+    pts = _points(9, 150, 320, 256, 8, x0=-32, y0=-32)
+    u = cgh.wasabi_hologram_fused(gpu, _q_gpu(gpu, pts), 0, 0, 256, 192).cpu().numpy()
+    want = orc.wasabi(ref, orc.quantize(pts, ref.params), 0, 0, 256, 192)
+    assert _rel(u, want) < 1e-4
+
+
+def test_2048_workload_sampled_windows(orc):
+    """The 2048^2, N = 10^4, 64-plane, L = 3, gamma = 5% workload at full size (oracle LUT
+    imported); the oracle computes four 128 x 128 windows (Haar windows are exact)."""
+    w = WASABI_2048
+    kw = dict(n_depth=w["n_depth"], levels=w["levels"], gamma=w["gamma"], max_window=w["max_window"])
+    ref = orc.build_lut(orc.LutParams(**kw))
+    gpu = cgh.wasabi_lut_import(cgh.LutParams(**kw), ref.off, ref.idx, ref.val)
+    pts = grid_points(w["seed"], w["n"], w["nx"], w["ny"], 8, w["z_lo"], w["z_hi"])
+    q = _q_gpu(gpu, pts)
+    full = cgh.wasabi_hologram_fused(gpu, q, 0, 0, w["nx"], w["ny"]).cpu().numpy()
+    split = cgh.wasabi_hologram(gpu, q, 0, 0, w["nx"], w["ny"], sub=1024).cpu().numpy()
+    oq = orc.quantize(pts, ref.params)
+    rng = np.random.default_rng(11)
+    for k in range(4):
+        y0, x0 = (int(v) * 8 for v in rng.integers(0, (w["nx"] - 128) // 8, 2))
+        want = orc.wasabi(ref, oq, x0, y0, 128, 128)
+        assert _rel(full[y0:y0 + 128, x0:x0 + 128], want) < TOL, (k, x0, y0)
+        assert _rel(split[y0:y0 + 128, x0:x0 + 128], want) < TOL, (k, x0, y0)
