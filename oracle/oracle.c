@@ -117,6 +117,8 @@ int oracle_lut_geometry(double wavelength, double pitch, double z_min, double z_
 /* ------------------------------------------------------------------------------------------
  * PSF table (Sec. 2, step 1):  T[r][q] = exp(i 2 pi / lambda * sqrt(((q-c)p)^2 + ((r-c)p)^2 + z^2))
  * when (q-c)^2 + (r-c)^2 < R^2 (circ(c) = 1 iff c < 1), else 0.  c = W / 2.
+ * The phase is taken modulo one revolution before the cosine and sine: the same value, but the
+ * thousands of whole revolutions no longer cost FP64 digits.
  * ---------------------------------------------------------------------------------------- */
 void oracle_psf_table(double z, double R, int32_t W, double pitch, double wavelength, double *T)
 {
@@ -126,10 +128,12 @@ void oracle_psf_table(double z, double R, int32_t W, double pitch, double wavele
             const double dq = (double)(q - c), dr = (double)(r - c);
             double re = 0.0, im = 0.0;
             if (dq * dq + dr * dr < R * R) {
+                /* phase 2 pi dist / lambda, whole revolutions removed first (an exact step) */
                 const double dist = sqrt((dq * pitch) * (dq * pitch) + (dr * pitch) * (dr * pitch) + z * z);
-                const double phase = 2.0 * M_PI * dist / wavelength;
-                re = cos(phase);
-                im = sin(phase);
+                const double rev = dist / wavelength;
+                const double frac = rev - floor(rev);
+                re = cos(2.0 * M_PI * frac);
+                im = sin(2.0 * M_PI * frac);
             }
             T[2 * ((int64_t)r * W + q) + 0] = re;
             T[2 * ((int64_t)r * W + q) + 1] = im;
@@ -204,11 +208,14 @@ void oracle_haar_inverse(double *A, int32_t h, int32_t w, int32_t levels)
 }
 
 /* ------------------------------------------------------------------------------------------
- * Shrinkage (Sec. 2, step 1): keep the N_r coefficients of largest magnitude.  Magnitudes are
- * compared as |c|^2 in FP64; equal magnitudes go to the lower flat index (idx = row * W + col).
- * The kept entries are written sorted by flat index.  C: W x W complex.
+ * Shrinkage (Sec. 2, step 1): keep the N_r strongest coefficients.  Strength is |c|^2 computed
+ * in FP64 and rounded to single precision (24 significant bits); equal strengths go to the lower
+ * flat index (idx = row * W + col).  The rounding makes coefficients that are equal in exact
+ * arithmetic (e.g. the transposed twins of the symmetric PSF) compare equal, so the kept set
+ * does not depend on last-bit rounding noise.  The kept entries are written sorted by flat
+ * index.  C: W x W complex.
  * ---------------------------------------------------------------------------------------- */
-typedef struct { double mag2; int32_t idx; } mag_entry;
+typedef struct { float mag2; int32_t idx; } mag_entry;
 
 static int by_magnitude_then_index(const void *pa, const void *pb)
 {
@@ -229,7 +236,7 @@ void oracle_select(const double *C, int32_t W, int64_t Nr, int32_t *idx_out, dou
     const int64_t all = (int64_t)W * W;
     mag_entry *e = (mag_entry *)malloc(sizeof(mag_entry) * (size_t)all);
     for (int64_t k = 0; k < all; k++) {
-        e[k].mag2 = C[2 * k] * C[2 * k] + C[2 * k + 1] * C[2 * k + 1];
+        e[k].mag2 = (float)(C[2 * k] * C[2 * k] + C[2 * k + 1] * C[2 * k + 1]);
         e[k].idx = (int32_t)k;
     }
     qsort(e, (size_t)all, sizeof(mag_entry), by_magnitude_then_index);

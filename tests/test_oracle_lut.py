@@ -69,6 +69,13 @@ def test_selection_is_best_k_by_magnitude(orc):
     D[1, 1] = D[0, 3] = D[2, 0] = 1.0
     idx2, _ = orc.select(D, 2)
     assert idx2.tolist() == [3, 5]
+    # strengths equal to single precision count as tied, whichever is larger in FP64
+    E = np.zeros((4, 4), complex)
+    E[3, 3] = 1.0 + 1e-12
+    E[1, 2] = 1.0
+    E[0, 0] = 0.5
+    idx3, _ = orc.select(E, 1)
+    assert idx3.tolist() == [6]
 
 
 def test_storage_rounding(orc):
