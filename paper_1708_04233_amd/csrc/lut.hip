@@ -3,9 +3,13 @@
 //  psf_haar_kernel : PSF table  exp(i 2 pi r / lambda) circ()  sampled in FP64 and transformed
 //                    by an L-level orthonormal Haar transform, one aligned 2^L x 2^L block at a
 //                    time in LDS (Haar blocks are independent, so no halo is needed).
-//  select_kernel   : per plane, the N_r largest |c|^2 by an 8-pass MSB radix select on the FP64
-//                    bit patterns, then an order-preserving compaction that writes (value, key)
-//                    entries grouped by Haar block and the per-block offsets.
+//  select_kernel   : per plane, the N_r strongest coefficients.  Strength is |c|^2 (FP64)
+//                    rounded to FP32, so coefficients equal in exact arithmetic (the PSF's
+//                    transposed twins) compare equal; equal strengths go to the lower flat table
+//                    index.  A 4-pass MSB radix select finds the threshold strength, a second
+//                    radix select over flat indices splits the tie at the threshold, and an
+//                    order-preserving compaction writes (value, key) entries grouped by Haar
+//                    block plus the per-block offsets.
 //  quantize_kernel : points (metres) -> grid position and plane index.
 #include <algorithm>
 #include <cmath>
@@ -69,11 +73,34 @@ inline double bf16_bits_to_f64(uint32_t h)
     return (double)x;
 }
 
+// (block row, block column, in-block code) -> flat index row * W + col of the plane's
+// Mallat-layout table.
+__host__ __device__ inline int64_t block_to_flat(int br, int bc, int code, int W, int L)
+{
+    const int B = 1 << L;
+    const int ir = code / B, ic = code % B;
+    int lev = L, band = 0, mm = ir, nn = ic;
+    for (int l = 1; l <= L; ++l) {
+        const int h = B >> l;
+        if (ir >= h || ic >= h) {
+            lev = l;
+            band = 2 * (ir >= h) + (ic >= h);
+            mm = ir - (ir >= h ? h : 0);
+            nn = ic - (ic >= h ? h : 0);
+            break;
+        }
+    }
+    const int h = B >> lev, s = W >> lev;
+    const int64_t row = ((band & 2) ? s : 0) + (int64_t)br * h + mm;
+    const int64_t col = ((band & 1) ? s : 0) + (int64_t)bc * h + nn;
+    return row * W + col;
+}
+
 // ---- PSF table + in-block forward Haar ------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(256) void psf_haar_kernel(int W, int nb, double z, double R2,
-                                                       double pitch, double inv_lambda,
-                                                       double2 *coef, double *mag2)
+                                                       double pitch, double lambda,
+                                                       double2 *coef, uint32_t *magq)
 {
     constexpr int B = 1 << L, BB = B * B;
     constexpr int G = BB >= 256 ? 1 : 256 / BB;  // blocks per workgroup
@@ -94,7 +121,7 @@ __global__ __launch_bounds__(256) void psf_haar_kernel(int W, int nb, double z, 
             const double dq = (double)(bc * B + code % B - c);
             if (dq * dq + dr * dr < R2) {
                 const double dist = sqrt((dq * pitch) * (dq * pitch) + (dr * pitch) * (dr * pitch) + z * z);
-                const double t = dist * inv_lambda;
+                const double t = dist / lambda;  // revolutions; whole ones dropped below
                 double s, cs;
                 sincospi(2.0 * (t - floor(t)), &s, &cs);
                 v = make_double2(cs, s);
@@ -144,7 +171,8 @@ __global__ __launch_bounds__(256) void psf_haar_kernel(int W, int nb, double z, 
             const double2 v = buf[p];
             const int64_t at = blk * BB + p % BB;
             coef[at] = v;
-            mag2[at] = v.x * v.x + v.y * v.y;
+            // strength key: |c|^2 rounded to FP32 (non-negative, so its bits order like its value)
+            magq[at] = __float_as_uint((float)(v.x * v.x + v.y * v.y));
         }
     }
 }
@@ -180,35 +208,37 @@ struct SelPlane {
 };
 
 template <int VT>
-__global__ __launch_bounds__(1024) void select_kernel(const double2 *coef_all, const double *mag2_all,
+__global__ __launch_bounds__(1024) void select_kernel(const double2 *coef_all, const uint32_t *magq_all,
                                                       const SelPlane *planes, int L,
                                                       void *values_all, uint16_t *keys_all,
                                                       int32_t *blk_off_all)
 {
     const SelPlane pl = planes[blockIdx.x];
     const double2 *coef = coef_all + pl.coef_off;
-    const double *mag2 = mag2_all + pl.coef_off;
+    const uint32_t *mq = magq_all + pl.coef_off;
     const int64_t count = pl.count, nr = pl.nr;
-    const int nb = pl.nb;
+    const int nb = pl.nb, W = nb << L;
     uint16_t *keys = keys_all + pl.entry_base;
     int32_t *blk_off = blk_off_all + pl.blkoff_base;
     void *values = (char *)values_all + (VT == CGH_F32 ? 8 : 4) * pl.entry_base;
+    const int BB = 1 << (2 * L);
+    const int BS = block_stride(L);
     __shared__ uint32_t hist[256];
     __shared__ int wave_tot[16];
     __shared__ int s_digit;
-    __shared__ long long s_k;
-    const uint64_t *bits = (const uint64_t *)mag2;
+    __shared__ long long s_k, s_ties;
 
-    // MSB-first radix select: after 8 passes `prefix` is the bit pattern of the nr-th largest
-    // magnitude and k the number of entries equal to it that still have to be taken.
-    uint64_t prefix = 0, mask = 0;
+    // (1) MSB-first radix select on the strength keys: `thr` is the key of the nr-th strongest
+    //     coefficient, `need` how many coefficients with key == thr are kept, `ties` how many
+    //     have key == thr.
+    uint32_t prefix = 0, mask = 0;
     long long k = nr;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 56 - 8 * pass;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
         for (int i = threadIdx.x; i < 256; i += 1024) hist[i] = 0;
         __syncthreads();
         for (int64_t i = threadIdx.x; i < count; i += 1024) {
-            const uint64_t b = bits[i];
+            const uint32_t b = mq[i];
             if ((b & mask) == prefix) atomicAdd(&hist[(b >> shift) & 255], 1u);
         }
         __syncthreads();
@@ -221,28 +251,69 @@ __global__ __launch_bounds__(1024) void select_kernel(const double2 *coef_all, c
             }
             s_digit = v;
             s_k = k - cum;
+            s_ties = hist[v];
         }
         __syncthreads();
-        prefix |= (uint64_t)s_digit << shift;
-        mask |= UINT64_C(255) << shift;
+        prefix |= (uint32_t)s_digit << shift;
+        mask |= 0xffu << shift;
         k = s_k;
         __syncthreads();
     }
-    const uint64_t thr = prefix;
-    const long long need_ties = k;
+    const uint32_t thr = prefix;
+    const long long need = k, ties = s_ties;
 
-    // order-preserving compaction; ties at the threshold are taken in coefficient order
-    const int BB = 1 << (2 * L);
-    const int BS = block_stride(L);
-    long long running = 0, ties_seen = 0;
+    // (2) equal strengths go to the lower flat table index: `fthr` is the need-th smallest flat
+    //     index among the tied coefficients (radix select from the low end).
+    uint32_t fthr = 0xffffffffu;
+    if (need < ties) {
+        uint32_t fp = 0, fm = 0;
+        long long kk = need;
+        for (int pass = 0; pass < 4; ++pass) {
+            const int shift = 24 - 8 * pass;
+            for (int i = threadIdx.x; i < 256; i += 1024) hist[i] = 0;
+            __syncthreads();
+            for (int64_t i = threadIdx.x; i < count; i += 1024) {
+                if (mq[i] != thr) continue;
+                const int64_t blk = i / BB;
+                const uint32_t f = (uint32_t)block_to_flat((int)(blk / nb), (int)(blk % nb), (int)(i % BB), W, L);
+                if ((f & fm) == fp) atomicAdd(&hist[(f >> shift) & 255], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                long long cum = 0;
+                int v = 0;
+                for (; v < 255; ++v) {
+                    if (cum + (long long)hist[v] >= kk) break;
+                    cum += hist[v];
+                }
+                s_digit = v;
+                s_k = kk - cum;
+            }
+            __syncthreads();
+            fp |= (uint32_t)s_digit << shift;
+            fm |= 0xffu << shift;
+            kk = s_k;
+            __syncthreads();
+        }
+        fthr = fp;
+    }
+
+    // (3) order-preserving compaction into (value, key) entries grouped by Haar block
+    long long running = 0;
     for (int64_t base = 0; base < count; base += 1024) {
         const int64_t i = base + threadIdx.x;
         const bool valid = i < count;
-        const uint64_t b = valid ? bits[i] : 0;
-        const bool gt = valid && b > thr, eq = valid && b == thr;
-        int tie_total, sel_total;
-        const int tie_before = block_excl_count(eq, wave_tot, tie_total);
-        const bool take = gt || (eq && ties_seen + tie_before < need_ties);
+        const uint32_t b = valid ? mq[i] : 0;
+        bool take = valid && b > thr;
+        if (valid && b == thr) {
+            if (need >= ties) {
+                take = true;
+            } else {
+                const int64_t blk = i / BB;
+                take = (uint32_t)block_to_flat((int)(blk / nb), (int)(blk % nb), (int)(i % BB), W, L) <= fthr;
+            }
+        }
+        int sel_total;
         const int sel_before = block_excl_count(take, wave_tot, sel_total);
         const long long pos = running + sel_before;
         if (valid && (i % BB) == 0) blk_off[i / BB] = (int32_t)pos;
@@ -260,7 +331,6 @@ __global__ __launch_bounds__(1024) void select_kernel(const double2 *coef_all, c
             }
         }
         running += sel_total;
-        ties_seen += tie_total;
     }
     if (threadIdx.x == 0) blk_off[count / BB] = (int32_t)running;
 }
@@ -316,27 +386,6 @@ void flat_to_block(int64_t flat, int W, int L, int &br, int &bc, int &code)
     const int ir = ((band & 2) ? h : 0) + m % h;
     const int ic = ((band & 1) ? h : 0) + n % h;
     code = ir * B + ic;
-}
-
-int64_t block_to_flat(int br, int bc, int code, int W, int L)
-{
-    const int B = 1 << L;
-    const int ir = code / B, ic = code % B;
-    int lev = L, band = 0, mm = ir, nn = ic;
-    for (int l = 1; l <= L; ++l) {
-        const int h = B >> l;
-        if (ir >= h || ic >= h) {
-            lev = l;
-            band = 2 * (ir >= h) + (ic >= h);
-            mm = ir - (ir >= h ? h : 0);
-            nn = ic - (ic >= h ? h : 0);
-            break;
-        }
-    }
-    const int h = B >> lev, s = W >> lev;
-    const int64_t row = ((band & 2) ? s : 0) + (int64_t)br * h + mm;
-    const int64_t col = ((band & 1) ? s : 0) + (int64_t)bc * h + nn;
-    return row * W + col;
 }
 
 size_t value_bytes(int vt) { return vt == CGH_F32 ? 8 : 4; }
@@ -426,15 +475,15 @@ wasabi_lut *new_lut(const wasabi_lut_params *prm)
 }
 
 template <int L>
-void launch_psf_haar(int W, int nb, double z, double R2, double pitch, double inv_lambda,
-                     double2 *coef, double *mag2, hipStream_t s)
+void launch_psf_haar(int W, int nb, double z, double R2, double pitch, double lambda,
+                     double2 *coef, uint32_t *magq, hipStream_t s)
 {
     constexpr int BB = 1 << (2 * L);
     constexpr int G = BB >= 256 ? 1 : 256 / BB;
     const int64_t nblk = (int64_t)nb * nb;
     const unsigned grid = (unsigned)((nblk + G - 1) / G);
     hipLaunchKernelGGL(psf_haar_kernel<L>, dim3(grid), dim3(256), 0, s, W, nb, z, R2, pitch,
-                       inv_lambda, coef, mag2);
+                       lambda, coef, magq);
 }
 
 }  // namespace
@@ -462,10 +511,10 @@ extern "C" int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, 
     for (int d = 0; d < n; ++d) coef_off[d + 1] = coef_off[d] + (int64_t)lut->W[d] * lut->W[d];
     coef_total = coef_off[n];
     double2 *coef = nullptr;
-    double *mag2 = nullptr;
+    uint32_t *mag2 = nullptr;
     {
         hipError_t e1 = hipMalloc((void **)&coef, sizeof(double2) * coef_total);
-        hipError_t e2 = hipMalloc((void **)&mag2, sizeof(double) * coef_total);
+        hipError_t e2 = hipMalloc((void **)&mag2, sizeof(uint32_t) * coef_total);
         if (e1 != hipSuccess || e2 != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(coef);
@@ -474,20 +523,20 @@ extern "C" int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, 
             return fail(CGH_ENOMEM, "LUT build scratch of %lld coefficients failed", (long long)coef_total);
         }
     }
-    const double inv_lambda = 1.0 / prm->wavelength;
+    const double lambda = prm->wavelength;
     std::vector<SelPlane> planes(n);
     for (int d = 0; d < n && !rc; ++d) {
         const int W = lut->W[d], nb = W / lut->B;
         const double R2 = lut->R[d] * lut->R[d];
         double2 *c = coef + coef_off[d];
-        double *m2 = mag2 + coef_off[d];
+        uint32_t *m2 = mag2 + coef_off[d];
         switch (L) {
-        case 1: launch_psf_haar<1>(W, nb, lut->z[d], R2, prm->pitch, inv_lambda, c, m2, s); break;
-        case 2: launch_psf_haar<2>(W, nb, lut->z[d], R2, prm->pitch, inv_lambda, c, m2, s); break;
-        case 3: launch_psf_haar<3>(W, nb, lut->z[d], R2, prm->pitch, inv_lambda, c, m2, s); break;
-        case 4: launch_psf_haar<4>(W, nb, lut->z[d], R2, prm->pitch, inv_lambda, c, m2, s); break;
-        case 5: launch_psf_haar<5>(W, nb, lut->z[d], R2, prm->pitch, inv_lambda, c, m2, s); break;
-        default: launch_psf_haar<6>(W, nb, lut->z[d], R2, prm->pitch, inv_lambda, c, m2, s); break;
+        case 1: launch_psf_haar<1>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 2: launch_psf_haar<2>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 3: launch_psf_haar<3>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 4: launch_psf_haar<4>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 5: launch_psf_haar<5>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        default: launch_psf_haar<6>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = fail(CGH_EHIP, "psf_haar_kernel: %s", hipGetErrorString(e));
