@@ -176,6 +176,18 @@ int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, in
                           int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *u_dev,
                           int64_t ld_u, void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Kernel tracing.  While enabled, the library records a pair of HIP events on the launching
+ * stream around each of its kernels (or kernel groups), under these names:
+ *   "direct", "quantize", "psf_haar", "select", "bin" (count + scan + fill), "tile_superpose",
+ *   "tile_fused", "idwt".
+ * cgh_profile_query synchronises the recorded events and returns the summed elapsed time and the
+ * number of launches for `name` (0 / 0 if none).  Not for concurrent use from several threads.
+ * ------------------------------------------------------------------------------------------- */
+int cgh_profile_enable(int32_t on);
+int cgh_profile_reset(void);
+int cgh_profile_query(const char *name, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

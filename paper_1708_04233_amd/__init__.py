@@ -73,6 +73,9 @@ def load() -> ctypes.CDLL:
         "wasabi_idwt": ([P, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram": ([P, P, I64, I64, I64, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram_fused": ([P, P, I64, I64, I64, I32, I32, P, I64, P], ctypes.c_int),
+        "cgh_profile_enable": ([I32], ctypes.c_int),
+        "cgh_profile_reset": ([], ctypes.c_int),
+        "cgh_profile_query": ([ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -110,6 +113,22 @@ def _dev(t: torch.Tensor, name: str, dtype=None, shape=None):
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
     return ctypes.c_void_p(t.data_ptr())
+
+
+def cgh_profile_enable(on: bool = True):
+    _check(load().cgh_profile_enable(1 if on else 0))
+
+
+def cgh_profile_reset():
+    _check(load().cgh_profile_reset())
+
+
+def cgh_profile_query(name: str):
+    """(total milliseconds, launches) recorded for kernel group `name` since the last reset."""
+    t = ctypes.c_double()
+    k = ctypes.c_int64()
+    _check(load().cgh_profile_query(name.encode(), ctypes.byref(t), ctypes.byref(k)))
+    return t.value, k.value
 
 
 # ----------------------------------------------------------------------------------------------

@@ -49,6 +49,18 @@ class Scratch {
 // Keeps the default pool's memory cached between calls (release threshold = unlimited).
 int prepare_pool();
 
+// Records a HIP event pair around the enclosed launches on `s` while tracing is enabled.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr;
+};
+
 // ---------------------------------------------------------------------------------------------
 // Coefficient LUT, device layout.
 //

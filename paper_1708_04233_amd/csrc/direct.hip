@@ -180,6 +180,7 @@ extern "C" int cgh_direct(const double *pts, int64_t n, int32_t nx, int32_t ny, 
     dim3 grid((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY);
     if (grid.y > 65535) return fail(CGH_EINVAL, "ny too large");
     const bool f64 = out_dtype == CGH_C128, circ = window == CGH_CIRC;
+    ProfScope prof("direct", s);
     if (circ && f64) hipLaunchKernelGGL((direct_kernel<true, true>), grid, dim3(kThreads), 0, s, a);
     else if (circ) hipLaunchKernelGGL((direct_kernel<true, false>), grid, dim3(kThreads), 0, s, a);
     else if (f64) hipLaunchKernelGGL((direct_kernel<false, true>), grid, dim3(kThreads), 0, s, a);

@@ -482,6 +482,7 @@ void launch_psf_haar(int W, int nb, double z, double R2, double pitch, double la
     constexpr int G = BB >= 256 ? 1 : 256 / BB;
     const int64_t nblk = (int64_t)nb * nb;
     const unsigned grid = (unsigned)((nblk + G - 1) / G);
+    ProfScope prof("psf_haar", s);
     hipLaunchKernelGGL(psf_haar_kernel<L>, dim3(grid), dim3(256), 0, s, W, nb, z, R2, pitch,
                        lambda, coef, magq);
 }
@@ -557,6 +558,7 @@ extern "C" int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, 
         if (e != hipSuccess) rc = fail(CGH_EHIP, "plane table upload: %s", hipGetErrorString(e));
     }
     if (!rc) {
+        ProfScope prof("select", s);
         if (prm->value_dtype == CGH_F32)
             hipLaunchKernelGGL(select_kernel<CGH_F32>, dim3(n), dim3(1024), 0, s, coef, mag2, planes_dev, L, lut->values, lut->keys, lut->blk_off);
         else if (prm->value_dtype == CGH_F16)
@@ -783,6 +785,7 @@ extern "C" int wasabi_quantize(const wasabi_lut *lut, const double *pts, int64_t
     const int threads = 256;
     const int64_t blocks = (n + threads - 1) / threads;
     if (blocks > INT32_MAX) return fail(CGH_EINVAL, "n too large");
+    ProfScope prof("quantize", (hipStream_t)stream);
     hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(threads), 0, (hipStream_t)stream,
                        (const double4 *)pts, n, p.pitch, p.z_min, p.z_max, dz, p.n_depth, lut->L, out);
     CGH_CHECK_LAUNCH("quantize_kernel");

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <string>
 
 #include "common.hpp"
 
@@ -54,6 +55,39 @@ int prepare_pool()
     CGH_TRY_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
     done.push_back(dev);
     return CGH_OK;
+}
+
+// ---- kernel tracing ---------------------------------------------------------------------------
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+
+ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), s_(s)
+{
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a_) != hipSuccess || hipEventRecord(a_, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        if (a_) (void)hipEventDestroy(a_);
+        a_ = nullptr;
+    }
+}
+
+ProfScope::~ProfScope()
+{
+    if (!a_) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(a_);
+        if (b) (void)hipEventDestroy(b);
+        return;
+    }
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_prof.push_back(ProfRec{name_, a_, b});
 }
 
 int validate_params(const wasabi_lut_params *prm)
@@ -120,3 +154,41 @@ int lut_geometry(wasabi_lut *lut)
 }  // namespace cgh
 
 extern "C" const char *cgh_last_error(void) { return cgh::g_msg; }
+
+extern "C" int cgh_profile_enable(int32_t on)
+{
+    cgh::g_prof_on = on != 0;
+    return CGH_OK;
+}
+
+extern "C" int cgh_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lock(cgh::g_prof_mu);
+    for (auto &r : cgh::g_prof) {
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    cgh::g_prof.clear();
+    return CGH_OK;
+}
+
+extern "C" int cgh_profile_query(const char *name, double *total_ms, int64_t *launches)
+{
+    using namespace cgh;
+    if (!name || !total_ms || !launches) return fail(CGH_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    double t = 0.0;
+    int64_t k = 0;
+    for (auto &r : g_prof) {
+        if (r.name != name) continue;
+        CGH_TRY_HIP(hipEventSynchronize(r.b));
+        float ms = 0.0f;
+        CGH_TRY_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        t += ms;
+        ++k;
+    }
+    *total_ms = t;
+    *launches = k;
+    return CGH_OK;
+}

@@ -414,6 +414,7 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     if ((rc = sc.alloc((void **)&bsum, sizeof(int64_t) * nblk))) return rc;
     if ((rc = sc.alloc((void **)&cursor, sizeof(unsigned long long) * ntiles))) return rc;
     if ((rc = sc.alloc((void **)&list, sizeof(int32_t) * bound))) return rc;
+    ProfScope prof("bin", s);
     CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
     const int nd = lut->prm.n_depth, L = lut->L;
     const unsigned pblocks = (unsigned)((n + 255) / 256);
@@ -451,6 +452,7 @@ int launch_tile(int L, int vt, const TileArgs &a, hipStream_t s)
     const int64_t ntiles = (int64_t)a.g.ntx * a.g.nty;
     if (ntiles > INT32_MAX) return fail(CGH_EINVAL, "too many tiles");
     const unsigned grid = (unsigned)ntiles;
+    ProfScope prof(MODE == MODE_PSI ? "tile_superpose" : "tile_fused", s);
     switch (L) {
     case 1: launch_tile_l<1, MODE>(vt, a, grid, s); break;
     case 2: launch_tile_l<2, MODE>(vt, a, grid, s); break;
@@ -520,6 +522,7 @@ int idwt_impl(const void *psi, int32_t nx, int32_t ny, int32_t levels, void *u, 
     const int64_t ntiles = (int64_t)g.ntx * g.nty;
     if (ntiles > INT32_MAX) return fail(CGH_EINVAL, "too many tiles");
     const dim3 grid((unsigned)ntiles);
+    ProfScope prof("idwt", s);
     switch (levels) {
     case 1: hipLaunchKernelGGL(idwt_kernel<1>, grid, dim3(kThreads), 0, s, a); break;
     case 2: hipLaunchKernelGGL(idwt_kernel<2>, grid, dim3(kThreads), 0, s, a); break;
