@@ -26,7 +26,8 @@ namespace cgh {
 namespace {
 
 constexpr int kT = 64;  // tile side, pixels
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;       // idwt workgroup
+constexpr int kTileThreads = 1024;  // superposition workgroup (16 waves; two fit a CU)
 constexpr int MODE_PSI = 0, MODE_FUSED = 1;
 
 struct TileGeom {
@@ -55,30 +56,147 @@ __device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, i
     return true;
 }
 
-__global__ void bin_count_kernel(const wasabi_point *pts, int64_t n, const DepthDesc *desc,
-                                 int n_depth, int L, TileGeom g, int32_t *counts)
+constexpr int kMaxLdsTiles = 4096;   // per-workgroup tile histograms live in LDS up to this
+constexpr int kDepthChunk = 8192;     // points per workgroup in the plane sort
+
+// ---- plane sort: points grouped by plane (invalid ones last), so that the per-tile lists built
+//      from them come out in plane order and concurrently running tiles share LUT planes in L2 ----
+// Also records the largest |a| of the valid points (bit pattern of a non-negative float, which
+// orders like its value) for the fixed-point scale of the superposition.
+template <bool LDS>
+__global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *pts, int64_t n,
+                                                           int n_depth, int32_t *counts,
+                                                           unsigned *amax)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int ty0, ty1, tx0, tx1;
-    if (!footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) return;
-    for (int ty = ty0; ty < ty1; ++ty)
-        for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&counts[(int64_t)ty * g.ntx + tx], 1);
+    extern __shared__ int hist[];  // n_depth + 1 bins (LDS variant)
+    __shared__ unsigned wmax;
+    const int nbins = n_depth + 1;
+    if (threadIdx.x == 0) wmax = 0u;
+    if (LDS)
+        for (int i = threadIdx.x; i < nbins; i += 1024) hist[i] = 0;
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * kDepthChunk;
+    const int64_t j1 = min(n, j0 + kDepthChunk);
+    unsigned m = 0u;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
+        const wasabi_point p = pts[j];
+        int d = p.depth;
+        if (d < 0 || d >= n_depth) {
+            d = n_depth;
+        } else {
+            m = max(m, __float_as_uint(fabsf(p.a)));
+        }
+        if (LDS) atomicAdd(&hist[d], 1);
+        else atomicAdd(&counts[d], 1);
+    }
+    atomicMax(&wmax, m);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(amax, wmax);
+    if (LDS)
+        for (int i = threadIdx.x; i < nbins; i += 1024)
+            if (hist[i]) atomicAdd(&counts[i], hist[i]);
 }
 
-__global__ void bin_fill_kernel(const wasabi_point *pts, int64_t n, const DepthDesc *desc,
-                                int n_depth, int L, TileGeom g, unsigned long long *cursor,
-                                int32_t *list)
+template <bool LDS>
+__global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point *pts, int64_t n,
+                                                             int n_depth,
+                                                             unsigned long long *cursor,
+                                                             wasabi_point *sorted)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int ty0, ty1, tx0, tx1;
-    if (!footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) return;
-    for (int ty = ty0; ty < ty1; ++ty)
-        for (int tx = tx0; tx < tx1; ++tx) {
-            const unsigned long long slot = atomicAdd(&cursor[(int64_t)ty * g.ntx + tx], 1ull);
-            list[slot] = (int32_t)j;
+    extern __shared__ int sh[];  // LDS variant: local count[nbins] then base[nbins] (64-bit)
+    const int nbins = n_depth + 1;
+    int *cnt = sh;
+    unsigned long long *base = (unsigned long long *)(sh + ((nbins + 1) & ~1));
+    const int64_t j0 = (int64_t)blockIdx.x * kDepthChunk;
+    const int64_t j1 = min(n, j0 + kDepthChunk);
+    if (LDS) {
+        for (int i = threadIdx.x; i < nbins; i += 1024) cnt[i] = 0;
+        __syncthreads();
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
+            int d = pts[j].depth;
+            if (d < 0 || d >= n_depth) d = n_depth;
+            atomicAdd(&cnt[d], 1);
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nbins; i += 1024) {
+            if (cnt[i]) base[i] = atomicAdd(&cursor[i], (unsigned long long)cnt[i]);
+            cnt[i] = 0;
+        }
+        __syncthreads();
+    }
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
+        const wasabi_point p = pts[j];
+        int d = p.depth;
+        if (d < 0 || d >= n_depth) d = n_depth;
+        unsigned long long slot;
+        if (LDS) slot = base[d] + (unsigned long long)atomicAdd(&cnt[d], 1);
+        else slot = atomicAdd(&cursor[d], 1ull);
+        sorted[slot] = p;
+    }
+}
+
+// ---- per-tile point lists (counting sort by tile) -------------------------------------------
+template <bool LDS>
+__global__ __launch_bounds__(256) void bin_count_kernel(const wasabi_point *pts, int64_t n,
+                                                        const DepthDesc *desc, int n_depth, int L,
+                                                        TileGeom g, int32_t *counts)
+{
+    __shared__ int hist[LDS ? kMaxLdsTiles : 1];
+    const int ntiles = g.ntx * g.nty;
+    if (LDS) {
+        for (int i = threadIdx.x; i < ntiles; i += 256) hist[i] = 0;
+        __syncthreads();
+    }
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int ty0, ty1, tx0, tx1;
+    if (j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) {
+        for (int ty = ty0; ty < ty1; ++ty)
+            for (int tx = tx0; tx < tx1; ++tx) {
+                if (LDS) atomicAdd(&hist[ty * g.ntx + tx], 1);
+                else atomicAdd(&counts[(int64_t)ty * g.ntx + tx], 1);
+            }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < ntiles; i += 256)
+            if (hist[i]) atomicAdd(&counts[i], hist[i]);
+    }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, int64_t n,
+                                                       const DepthDesc *desc, int n_depth, int L,
+                                                       TileGeom g, unsigned long long *cursor,
+                                                       int32_t *list)
+{
+    __shared__ int cnt[LDS ? kMaxLdsTiles : 1];
+    __shared__ unsigned long long base[LDS ? kMaxLdsTiles : 1];
+    const int ntiles = g.ntx * g.nty;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int ty0 = 0, ty1 = 0, tx0 = 0, tx1 = 0;
+    const bool has = j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1);
+    if (LDS) {
+        for (int i = threadIdx.x; i < ntiles; i += 256) cnt[i] = 0;
+        __syncthreads();
+        if (has)
+            for (int ty = ty0; ty < ty1; ++ty)
+                for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&cnt[ty * g.ntx + tx], 1);
+        __syncthreads();
+        for (int i = threadIdx.x; i < ntiles; i += 256) {
+            if (cnt[i]) base[i] = atomicAdd(&cursor[i], (unsigned long long)cnt[i]);
+            cnt[i] = 0;
+        }
+        __syncthreads();
+    }
+    if (has)
+        for (int ty = ty0; ty < ty1; ++ty)
+            for (int tx = tx0; tx < tx1; ++tx) {
+                const int t = ty * g.ntx + tx;
+                unsigned long long slot;
+                if (LDS) slot = base[t] + (unsigned long long)atomicAdd(&cnt[t], 1);
+                else slot = atomicAdd(&cursor[(int64_t)ty * g.ntx + tx], 1ull);
+                list[slot] = (int32_t)j;
+            }
 }
 
 // ---- exclusive scan of int32 counts into int64 offsets (n + 1 values) ----------------------
@@ -148,6 +266,7 @@ struct TileArgs {
     const float2 *in;  // idwt: Mallat-layout field of the window (contiguous, row stride nx)
     float2 *out;       // MODE_PSI: Mallat field (row stride nx); otherwise pixels (row stride ld)
     int64_t ld;
+    const unsigned *amax;  // largest |a| of the points (float bits)
 };
 
 template <int L>
@@ -175,7 +294,7 @@ __device__ inline float2 load_value(const void *values, int64_t i)
 }
 
 // Moves the tile's coefficients between LDS and the window's Mallat layout (rows of nx).
-template <int L, bool TO_LDS>
+template <int L, bool TO_LDS, int NT>
 __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, const TileGeom &g,
                                       int ty, int tx, int th, int tw)
 {
@@ -188,7 +307,7 @@ __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, con
         const int hb = th >> l, wb = tw >> l;
         for (int band = 1; band <= 3; ++band) {
             const int64_t row0 = (band & 2) ? (g.ny >> l) : 0, col0 = (band & 1) ? (g.nx >> l) : 0;
-            for (int i = threadIdx.x; i < wf * wf; i += kThreads) {
+            for (int i = threadIdx.x; i < wf * wf; i += NT) {
                 const int m = i / wf, n = i % wf;
                 if (m >= hb || n >= wb) continue;
                 const int code = (((band & 2) ? h : 0) + (m & (h - 1))) * S::B + ((band & 1) ? h : 0) + (n & (h - 1));
@@ -207,7 +326,7 @@ __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, con
     {
         const int wf = kT >> L;
         const int hb = th >> L, wb = tw >> L;
-        for (int i = threadIdx.x; i < wf * wf; i += kThreads) {
+        for (int i = threadIdx.x; i < wf * wf; i += NT) {
             const int m = i / wf, n = i % wf;
             if (m >= hb || n >= wb) continue;
             const int at = m * S::ROW + n * S::BS;
@@ -224,12 +343,12 @@ __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, con
 }
 
 // In-LDS inverse Haar of every block of the tile, then the pixels go to out (row stride ld).
-template <int L>
+template <int L, int NT>
 __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *out, int64_t ld,
                                               int ty, int tx, int th, int tw)
 {
     using S = TileShape<L>;
-    constexpr int MAXQ = (kT * kT / 4 + kThreads - 1) / kThreads;
+    constexpr int MAXQ = (kT * kT / 4 + NT - 1) / NT;
 #pragma unroll
     for (int l = L; l >= 1; --l) {
         const int h = S::B >> l;           // S^(l) extent inside a block
@@ -239,7 +358,7 @@ __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *ou
         int base[MAXQ], mm[MAXQ], nn[MAXQ];
 #pragma unroll
         for (int k = 0; k < MAXQ; ++k) {
-            const int qi = threadIdx.x + kThreads * k;
+            const int qi = threadIdx.x + NT * k;
             if (qi < nq) {
                 const int blk = qi / per, w = qi % per;
                 const int m = w / h, n = w % h;
@@ -255,7 +374,7 @@ __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *ou
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MAXQ; ++k) {
-            const int qi = threadIdx.x + kThreads * k;
+            const int qi = threadIdx.x + NT * k;
             if (qi < nq) {
                 const int a00 = base[k] + (2 * mm[k]) * S::B + 2 * nn[k];
                 const int a10 = a00 + S::B;
@@ -273,7 +392,7 @@ __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *ou
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < kT * kT; i += kThreads) {
+    for (int i = threadIdx.x; i < kT * kT; i += NT) {
         const int rr = i / kT, cc = i % kT;
         if (rr >= th || cc >= tw) continue;
         const int at = (rr >> L) * S::ROW + (cc >> L) * S::BS + (rr & (S::B - 1)) * S::B + (cc & (S::B - 1));
@@ -281,79 +400,181 @@ __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *ou
     }
 }
 
-template <int L, int VT, int MODE>
-__global__ __launch_bounds__(kThreads) void tile_kernel(TileArgs a)
+// Fixed-point accumulation.  LDS float atomics are slow on this GPU, integer ones are not, so each
+// term a_j * c is formed exactly in FP64 (a product of two FP32 values), rounded once to the grid
+// 2^-s, and added as a 64-bit integer (ds_add_u64).  Integer sums are exact and independent of the
+// order of the adds.  The rounding uses the FP64 "magic number" 1.5 * 2^52: for |y| < 2^51,
+// bits(y + 1.5 * 2^52) - bits(1.5 * 2^52) is round-to-nearest-even(y) as an integer.
+constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+constexpr long long kMagicBits = 0x4338000000000000LL;
+
+__device__ inline long long to_fixed(float v, double scaled_amp)
+{
+    return __double_as_longlong(fma((double)v, scaled_amp, kMagic)) - kMagicBits;
+}
+
+// Scale exponent s: every term satisfies |a c| <= 2^e * 2^L with 2^e >= max|a| (e >= 0), so
+// |term| * 2^s < 2^40 keeps the rounding exact-range (< 2^51) and a coefficient's sum below 2^63
+// unless more than 2^22 terms pile up on it coherently.
+__device__ inline int fixed_shift(unsigned amax_bits, int L)
+{
+    const int E = (int)((amax_bits >> 23) & 255) - 127;  // max|a| < 2^(E+1)
+    const int e = max(0, E + 1);
+    return 40 - L - e;
+}
+
+// Adds the kept coefficients of one (tile, point) pair into the tile's LDS accumulators.  Called by
+// a whole wave with uniform arguments: the pair's table blocks inside the tile are `nrows` block
+// rows; row r's entries are the contiguous LUT range [rstart_r, rstart_r + rcount_r) (held by lane
+// r) and land at LDS element dst0 + r * ROW + key.  Each row is walked U x 64 entries at a time
+// with all loads issued before the LDS adds.
+template <int L, int VT>
+__device__ inline void add_pair(long long *are, long long *aim, const void *values,
+                                const uint16_t *keys, int eb, int dst0, int nrows,
+                                double scaled_amp, int rstart, int rcount)
 {
     using S = TileShape<L>;
-    __shared__ float sre[S::N];
-    __shared__ float sim[S::N];
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    for (int r = 0; r < nrows; ++r) {
+        const int rs = __builtin_amdgcn_readlane(rstart, r);
+        const int rc = __builtin_amdgcn_readlane(rcount, r);
+        const int d = dst0 + r * S::ROW;
+        const int64_t first = (int64_t)eb + rs;
+        const uint16_t *kp = keys + first;
+        for (int c = 0; c < rc; c += 64 * U) {
+            float2 v[U];
+            int k[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = c + 64 * u + lane;
+                if (e < rc) {
+                    v[u] = load_value<VT>(values, first + e);
+                    k[u] = kp[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = c + 64 * u + lane;
+                if (e < rc) {
+                    const int at = d + k[u];
+                    atomicAdd((unsigned long long *)&are[at], (unsigned long long)to_fixed(v[u].x, scaled_amp));
+                    atomicAdd((unsigned long long *)&aim[at], (unsigned long long)to_fixed(v[u].y, scaled_amp));
+                }
+            }
+        }
+    }
+}
+
+template <int L, int VT, int MODE>
+__global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
+{
+    using S = TileShape<L>;
+    constexpr int NW = kTileThreads / 64;
+    __shared__ long long acc[2 * S::N];  // fixed-point re plane, then im plane
+    long long *are = acc, *aim = acc + S::N;
     const int tile = blockIdx.x;
     const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int tbh = th >> L, tbw = tw >> L;
-    for (int i = threadIdx.x; i < S::N; i += kThreads) {
-        sre[i] = 0.0f;
-        sim[i] = 0.0f;
-    }
+    for (int i = threadIdx.x; i < 2 * S::N; i += kTileThreads) acc[i] = 0;
+    const int shift = fixed_shift(*a.amax, L);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
     const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
-    for (int64_t p = p0 + wave; p < p1; p += kThreads / 64) {
-        const wasabi_point pt = a.pts[a.tile_pts[p]];
-        const DepthDesc dd = a.desc[pt.depth];
-        const int64_t xg = (int64_t)(pt.x >> L) << L, yg = (int64_t)(pt.y >> L) << L;
-        const int obr = (int)((yg - dd.W / 2 - gy0) >> L);  // table block (0,0) in tile blocks
-        const int obc = (int)((xg - dd.W / 2 - gx0) >> L);
-        const int br0 = max(dd.br0, -obr), br1 = min(dd.br1, tbh - obr);
-        const int bc0 = max(dd.bc0, -obc), bc1 = min(dd.bc1, tbw - obc);
-        if (br0 >= br1 || bc0 >= bc1) continue;
-        const int nrows = br1 - br0;
+    // Waves take interleaved pairs (wave w: pairs w, w + NW, ...), so the waves of a tile work
+    // on neighbouring list positions, i.e. on the same LUT planes.  Each wave gathers the
+    // metadata of 64 pairs at once (one pair per lane), then walks them.
+    for (int64_t pb = p0 + wave; pb < p1; pb += 64 * NW) {
+        const int64_t pk = pb + (int64_t)lane * NW;
+        int m_nrows = 0, m_bo = 0, m_nb = 0, m_bc0 = 0, m_bc1 = 0, m_eb = 0, m_dst0 = 0;
+        float m_amp = 0.0f;
+        if (pk < p1) {
+            const wasabi_point pt = a.pts[a.tile_pts[pk]];
+            const DepthDesc dd = a.desc[pt.depth];
+            const int64_t xg = (int64_t)(pt.x >> L) << L, yg = (int64_t)(pt.y >> L) << L;
+            const int obr = (int)((yg - dd.W / 2 - gy0) >> L);  // table block (0,0) in tile blocks
+            const int obc = (int)((xg - dd.W / 2 - gx0) >> L);
+            const int br0 = max(dd.br0, -obr), br1 = min(dd.br1, tbh - obr);
+            const int bc0 = max(dd.bc0, -obc), bc1 = min(dd.bc1, tbw - obc);
+            if (br0 < br1 && bc0 < bc1) {
+                m_nrows = br1 - br0;
+                m_bo = (int)(dd.blkoff_base + (int64_t)br0 * dd.nb);
+                m_nb = dd.nb;
+                m_bc0 = bc0;
+                m_bc1 = bc1;
+                m_eb = (int)dd.entry_base;
+                m_dst0 = (br0 + obr) * S::ROW + obc * S::BS;
+                m_amp = pt.a;
+            }
+        }
+        const int cnt = (int)min((int64_t)64, (p1 - pb + NW - 1) / NW);
+        // software pipeline: the row ranges of the next pair load while this pair's entries run
+        int k = 0;
+        while (k < cnt && __builtin_amdgcn_readlane(m_nrows, k) == 0) ++k;
         int rstart = 0, rcount = 0;
-        if (lane < nrows) {
-            const int32_t *bo = a.blk_off + dd.blkoff_base + (int64_t)(br0 + lane) * dd.nb;
-            rstart = bo[bc0];
-            rcount = bo[bc1] - rstart;
+        if (k < cnt) {
+            const int nrows = __builtin_amdgcn_readlane(m_nrows, k);
+            if (lane < nrows) {
+                const int32_t *r = a.blk_off + __builtin_amdgcn_readlane(m_bo, k) + lane * __builtin_amdgcn_readlane(m_nb, k);
+                rstart = r[__builtin_amdgcn_readlane(m_bc0, k)];
+                rcount = r[__builtin_amdgcn_readlane(m_bc1, k)] - rstart;
+            }
         }
-        int incl = rcount;
-        for (int o = 1; o < S::TB; o <<= 1) {
-            const int t = __shfl_up(incl, o);
-            if (lane >= o) incl += t;
-        }
-        const int total = __builtin_amdgcn_readlane(incl, S::TB - 1);
-        if (total == 0) continue;
-        const float amp = pt.a;
-        const int64_t ebase = dd.entry_base;
-        const uint16_t *keys = a.keys + ebase;
-        const int dst0 = (br0 + obr) * S::ROW + obc * S::BS;
-        for (int base = 0; base < total; base += 64) {
-            const int e = base + lane;
-            int src = 0, dst = 0;
-            for (int r = 0; r < nrows; ++r) {
-                const int hi = __builtin_amdgcn_readlane(incl, r);
-                const int lo = hi - __builtin_amdgcn_readlane(rcount, r);
-                if (lo < base + 64 && hi > base && e >= lo) {
-                    src = __builtin_amdgcn_readlane(rstart, r) - lo;
-                    dst = dst0 + r * S::ROW;
+        while (k < cnt) {
+            int kn = k + 1;
+            while (kn < cnt && __builtin_amdgcn_readlane(m_nrows, kn) == 0) ++kn;
+            int nstart = 0, nend = 0;
+            if (kn < cnt) {
+                const int nrows = __builtin_amdgcn_readlane(m_nrows, kn);
+                if (lane < nrows) {
+                    const int32_t *r = a.blk_off + __builtin_amdgcn_readlane(m_bo, kn) + lane * __builtin_amdgcn_readlane(m_nb, kn);
+                    nstart = r[__builtin_amdgcn_readlane(m_bc0, kn)];
+                    nend = r[__builtin_amdgcn_readlane(m_bc1, kn)];
                 }
             }
-            if (e < total) {
-                const int li = src + e;
-                const float2 v = load_value<VT>(a.values, ebase + li);
-                const int at = dst + keys[li];
-                atomicAdd(&sre[at], amp * v.x);
-                atomicAdd(&sim[at], amp * v.y);
-            }
+            const float amp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k));
+            add_pair<L, VT>(are, aim, a.values, a.keys, __builtin_amdgcn_readlane(m_eb, k),
+                            __builtin_amdgcn_readlane(m_dst0, k), __builtin_amdgcn_readlane(m_nrows, k),
+                            ldexp((double)amp, shift), rstart, rcount);
+            rstart = nstart;
+            rcount = nend - nstart;
+            k = kn;
+        }
+    }
+    __syncthreads();
+
+    // fixed point -> FP32, in place: the float planes occupy the first half of `acc`
+    constexpr int PER = (S::N + kTileThreads - 1) / kTileThreads;
+    const double unscale = ldexp(1.0, -shift);
+    float fr[PER], fi[PER];
+#pragma unroll
+    for (int k2 = 0; k2 < PER; ++k2) {
+        const int i = threadIdx.x + k2 * kTileThreads;
+        if (i < S::N) {
+            fr[k2] = (float)((double)are[i] * unscale);
+            fi[k2] = (float)((double)aim[i] * unscale);
+        }
+    }
+    __syncthreads();
+    float *sre = (float *)acc, *sim = sre + S::N;
+#pragma unroll
+    for (int k2 = 0; k2 < PER; ++k2) {
+        const int i = threadIdx.x + k2 * kTileThreads;
+        if (i < S::N) {
+            sre[i] = fr[k2];
+            sim[i] = fi[k2];
         }
     }
     __syncthreads();
 
     if (MODE == MODE_PSI) {
-        tile_mallat_io<L, false>(sre, sim, a.out, a.g, ty, tx, th, tw);
+        tile_mallat_io<L, false, kTileThreads>(sre, sim, a.out, a.g, ty, tx, th, tw);
     } else {
-        tile_inverse_and_store<L>(sre, sim, a.out, a.ld, ty, tx, th, tw);
+        tile_inverse_and_store<L, kTileThreads>(sre, sim, a.out, a.ld, ty, tx, th, tw);
     }
 }
 
@@ -366,9 +587,9 @@ __global__ __launch_bounds__(kThreads) void idwt_kernel(TileArgs a)
     const int tile = blockIdx.x;
     const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
-    tile_mallat_io<L, true>(sre, sim, const_cast<float2 *>(a.in), a.g, ty, tx, th, tw);
+    tile_mallat_io<L, true, kThreads>(sre, sim, const_cast<float2 *>(a.in), a.g, ty, tx, th, tw);
     __syncthreads();
-    tile_inverse_and_store<L>(sre, sim, a.out, a.ld, ty, tx, th, tw);
+    tile_inverse_and_store<L, kThreads>(sre, sim, a.out, a.ld, ty, tx, th, tw);
 }
 
 // ---- host side ------------------------------------------------------------------------------
@@ -395,55 +616,105 @@ int check_window(int L, int64_t ox, int64_t oy, int32_t nx, int32_t ny)
     return CGH_OK;
 }
 
-// Build the per-tile point lists; results live in `sc`.
+// Exclusive scan of `count` int32 values into int64 offsets (count + 1 values) on stream s.
+int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc, hipStream_t s)
+{
+    const int64_t nblk = (count + 1023) / 1024;
+    int64_t *bsum;
+    int rc = sc.alloc((void **)&bsum, sizeof(int64_t) * nblk);
+    if (rc) return rc;
+    hipLaunchKernelGGL(scan_local_kernel, dim3((unsigned)nblk), dim3(1024), 0, s, counts, count, off, bsum);
+    CGH_CHECK_LAUNCH("scan_local_kernel");
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nblk, off + count);
+    CGH_CHECK_LAUNCH("scan_sums_kernel");
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, off, count, bsum);
+    CGH_CHECK_LAUNCH("scan_add_kernel");
+    return CGH_OK;
+}
+
+// Plane-sort the points and build the per-tile point lists; results live in `sc`.
 int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,
-               Scratch &sc, hipStream_t s, int64_t **tile_off_out, int32_t **tile_pts_out)
+               Scratch &sc, hipStream_t s, const wasabi_point **sorted_out,
+               int64_t **tile_off_out, int32_t **tile_pts_out, const unsigned **amax_out)
 {
     const int64_t ntiles = (int64_t)g.ntx * g.nty;
     const int64_t per_side = (lut->max_span_px + kT - 1) / kT + 1;
     const int64_t per_point = std::min<int64_t>(per_side * per_side, ntiles);
     const int64_t bound = std::max<int64_t>(n * per_point, 1);
-    const int64_t nblk = (ntiles + 1023) / 1024;
-    int32_t *counts;
-    int64_t *off, *bsum;
-    unsigned long long *cursor;
+    const int nd = lut->prm.n_depth, L = lut->L;
+    const int nbins = nd + 1;
+    int32_t *counts, *dcounts;
+    int64_t *off, *doff;
+    unsigned long long *cursor, *dcursor;
     int32_t *list;
+    wasabi_point *sorted;
     int rc;
     if ((rc = sc.alloc((void **)&counts, sizeof(int32_t) * ntiles))) return rc;
     if ((rc = sc.alloc((void **)&off, sizeof(int64_t) * (ntiles + 1)))) return rc;
-    if ((rc = sc.alloc((void **)&bsum, sizeof(int64_t) * nblk))) return rc;
     if ((rc = sc.alloc((void **)&cursor, sizeof(unsigned long long) * ntiles))) return rc;
     if ((rc = sc.alloc((void **)&list, sizeof(int32_t) * bound))) return rc;
+    if ((rc = sc.alloc((void **)&dcounts, sizeof(int32_t) * nbins))) return rc;
+    if ((rc = sc.alloc((void **)&doff, sizeof(int64_t) * (nbins + 1)))) return rc;
+    if ((rc = sc.alloc((void **)&dcursor, sizeof(unsigned long long) * nbins))) return rc;
+    if ((rc = sc.alloc((void **)&sorted, sizeof(wasabi_point) * std::max<int64_t>(n, 1)))) return rc;
+    unsigned *amax;
+    if ((rc = sc.alloc((void **)&amax, sizeof(unsigned)))) return rc;
     ProfScope prof("bin", s);
+    // plane sort
+    CGH_TRY_HIP(hipMemsetAsync(dcounts, 0, sizeof(int32_t) * nbins, s));
+    CGH_TRY_HIP(hipMemsetAsync(amax, 0, sizeof(unsigned), s));
+    const bool lds_depth = nbins <= 4096;
+    const unsigned dgrid = (unsigned)std::max<int64_t>((n + kDepthChunk - 1) / kDepthChunk, 1);
+    if (n > 0) {
+        if (lds_depth)
+            hipLaunchKernelGGL(depth_count_kernel<true>, dim3(dgrid), dim3(1024), sizeof(int) * nbins, s, pts, n, nd, dcounts, amax);
+        else
+            hipLaunchKernelGGL(depth_count_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, nd, dcounts, amax);
+        CGH_CHECK_LAUNCH("depth_count_kernel");
+    }
+    if ((rc = scan_counts(dcounts, nbins, doff, sc, s))) return rc;
+    if (n > 0) {
+        CGH_TRY_HIP(hipMemcpyAsync(dcursor, doff, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
+        const size_t sh = sizeof(int) * ((nbins + 1) & ~1) + sizeof(unsigned long long) * nbins;
+        if (lds_depth)
+            hipLaunchKernelGGL(depth_scatter_kernel<true>, dim3(dgrid), dim3(1024), sh, s, pts, n, nd, dcursor, sorted);
+        else
+            hipLaunchKernelGGL(depth_scatter_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, nd, dcursor, sorted);
+        CGH_CHECK_LAUNCH("depth_scatter_kernel");
+    }
+    // tile lists over the plane-sorted points
     CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
-    const int nd = lut->prm.n_depth, L = lut->L;
+    const bool lds_tiles = ntiles <= kMaxLdsTiles;
     const unsigned pblocks = (unsigned)((n + 255) / 256);
     if (n > 0) {
-        hipLaunchKernelGGL(bin_count_kernel, dim3(pblocks), dim3(256), 0, s, pts, n, lut->desc, nd, L, g, counts);
+        if (lds_tiles)
+            hipLaunchKernelGGL(bin_count_kernel<true>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, counts);
+        else
+            hipLaunchKernelGGL(bin_count_kernel<false>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, counts);
         CGH_CHECK_LAUNCH("bin_count_kernel");
     }
-    hipLaunchKernelGGL(scan_local_kernel, dim3((unsigned)nblk), dim3(1024), 0, s, counts, ntiles, off, bsum);
-    CGH_CHECK_LAUNCH("scan_local_kernel");
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nblk, off + ntiles);
-    CGH_CHECK_LAUNCH("scan_sums_kernel");
-    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, off, ntiles, bsum);
-    CGH_CHECK_LAUNCH("scan_add_kernel");
+    if ((rc = scan_counts(counts, ntiles, off, sc, s))) return rc;
     if (n > 0) {
         CGH_TRY_HIP(hipMemcpyAsync(cursor, off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(bin_fill_kernel, dim3(pblocks), dim3(256), 0, s, pts, n, lut->desc, nd, L, g, cursor, list);
+        if (lds_tiles)
+            hipLaunchKernelGGL(bin_fill_kernel<true>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, cursor, list);
+        else
+            hipLaunchKernelGGL(bin_fill_kernel<false>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, cursor, list);
         CGH_CHECK_LAUNCH("bin_fill_kernel");
     }
+    *sorted_out = sorted;
     *tile_off_out = off;
     *tile_pts_out = list;
+    *amax_out = amax;
     return CGH_OK;
 }
 
 template <int L, int MODE>
 void launch_tile_l(int vt, const TileArgs &a, unsigned grid, hipStream_t s)
 {
-    if (vt == CGH_F32) hipLaunchKernelGGL((tile_kernel<L, CGH_F32, MODE>), dim3(grid), dim3(kThreads), 0, s, a);
-    else if (vt == CGH_F16) hipLaunchKernelGGL((tile_kernel<L, CGH_F16, MODE>), dim3(grid), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((tile_kernel<L, CGH_BF16, MODE>), dim3(grid), dim3(kThreads), 0, s, a);
+    if (vt == CGH_F32) hipLaunchKernelGGL((tile_kernel<L, CGH_F32, MODE>), dim3(grid), dim3(kTileThreads), 0, s, a);
+    else if (vt == CGH_F16) hipLaunchKernelGGL((tile_kernel<L, CGH_F16, MODE>), dim3(grid), dim3(kTileThreads), 0, s, a);
+    else hipLaunchKernelGGL((tile_kernel<L, CGH_BF16, MODE>), dim3(grid), dim3(kTileThreads), 0, s, a);
 }
 
 template <int MODE>
@@ -480,6 +751,7 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.in = nullptr;
     a.out = out;
     a.ld = ld;
+    a.amax = nullptr;
     return a;
 }
 
@@ -493,9 +765,12 @@ int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, in
     Scratch sc(s);
     int64_t *tile_off;
     int32_t *tile_pts;
-    rc = bin_points(lut, pts, n, g, sc, s, &tile_off, &tile_pts);
+    const wasabi_point *sorted;
+    const unsigned *amax;
+    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts, &amax);
     if (rc) return rc;
-    const TileArgs a = make_args(lut, pts, tile_off, tile_pts, g, (float2 *)out, ld);
+    TileArgs a = make_args(lut, sorted, tile_off, tile_pts, g, (float2 *)out, ld);
+    a.amax = amax;
     if (mode == MODE_PSI) return launch_tile<MODE_PSI>(lut->L, lut->prm.value_dtype, a, s);
     return launch_tile<MODE_FUSED>(lut->L, lut->prm.value_dtype, a, s);
 }
