@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--gamma", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--lut", choices=["f32", "f16", "bf16"], default="f32",
+                    help="LUT value storage (the 2048^2 workload is specified in FP32)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -144,8 +146,11 @@ def main():
     pts = torch.from_numpy(pts_np).cuda()
     mpp = nx * ny * n / 1e6  # Mpixel*points per hologram
 
+    vt = {"f32": cgh.F32, "f16": cgh.F16, "bf16": cgh.BF16}[args.lut]
+
     def lut_for(g):
-        prm = cgh.LutParams(n_depth=w["n_depth"], levels=L, gamma=g, max_window=w["max_window"])
+        prm = cgh.LutParams(n_depth=w["n_depth"], levels=L, gamma=g, max_window=w["max_window"],
+                            value_dtype=vt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lut = cgh.wasabi_build_lut(prm)
@@ -225,7 +230,7 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "algorithmic_bytes": algo_bytes,
                 "scatter_adds": scatter, "scatter_adds_per_s": round(scatter / t_tile, 1),
-                "lut_stream_GBps": round(scatter * 10 / t_tile / 1e9, 1),
+                "lut_stream_GBps": round(scatter * (10 if args.lut == "f32" else 6) / t_tile / 1e9, 1),
                 "ms_per_launch": round(kernels["tile_fused"], 4)}
 
     # ---- CPU baseline: the oracle on the same hologram ---------------------------------------
@@ -254,7 +259,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "global_batch": n, "hologram": [ny, nx],
                    "planes": w["n_depth"], "levels": L, "gamma": g40, "psnr_db": round(p40, 2),
-                   "lut_values": "f32", "lut_entries": int(info40["total_entries"]),
+                   "lut_values": args.lut, "lut_entries": int(info40["total_entries"]),
                    "lut_build_ms": round(build40_ms, 1), "path": "quantize+bin+fused superpose/inverse"},
         "ms_per_step_untraced": round(ms_untraced, 4),
         "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},

@@ -84,6 +84,8 @@ struct DepthDesc {
     int32_t nb;           // W / B
     int32_t br0, br1;     // block rows holding kept entries: [br0, br1)
     int32_t bc0, bc1;     // block columns holding kept entries: [bc0, bc1)
+    float cmax;           // largest |re| or |im| of the plane's stored values
+    int32_t pad;
     int64_t entry_base;   // first entry of the plane in values/keys
     int64_t blkoff_base;  // first element of the plane's blk_off array
 };

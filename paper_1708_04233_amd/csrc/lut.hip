@@ -335,6 +335,45 @@ __global__ __launch_bounds__(1024) void select_kernel(const double2 *coef_all, c
     if (threadIdx.x == 0) blk_off[count / BB] = (int32_t)running;
 }
 
+// ---- largest stored |re| / |im| per plane (one workgroup per plane) -------------------------
+template <int VT>
+__global__ __launch_bounds__(256) void plane_cmax_kernel(const void *values, const int64_t *entry_off,
+                                                         float *cmax)
+{
+    __shared__ float red[256];
+    const int64_t e0 = entry_off[blockIdx.x], e1 = entry_off[blockIdx.x + 1];
+    float m = 0.0f;
+    for (int64_t i = e0 + threadIdx.x; i < e1; i += 256) {
+        float re, im;
+        if (VT == CGH_F32) {
+            const float2 v = ((const float2 *)values)[i];
+            re = v.x;
+            im = v.y;
+        } else {
+            const uint32_t w = ((const uint32_t *)values)[i];
+            if (VT == CGH_F16) {
+                _Float16 lo, hi;
+                const uint16_t l16 = (uint16_t)(w & 0xffff), h16 = (uint16_t)(w >> 16);
+                __builtin_memcpy(&lo, &l16, 2);
+                __builtin_memcpy(&hi, &h16, 2);
+                re = (float)lo;
+                im = (float)hi;
+            } else {
+                re = __uint_as_float(w << 16);
+                im = __uint_as_float(w & 0xffff0000u);
+            }
+        }
+        m = fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cmax[blockIdx.x] = red[0];
+}
+
 // ---- quantisation ---------------------------------------------------------------------------
 __global__ void quantize_kernel(const double4 *pts, int64_t n, double pitch, double z_min,
                                 double z_max, double dz, int n_depth, int L, wasabi_point *out)
@@ -390,11 +429,31 @@ void flat_to_block(int64_t flat, int W, int L, int &br, int &bc, int &code)
 
 size_t value_bytes(int vt) { return vt == CGH_F32 ? 8 : 4; }
 
-// Fill the occupied block ranges and device descriptors from host blk_off; upload descriptors.
+// Fill the occupied block ranges, the per-plane value bound and the device descriptors.
 int finish_lut(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
 {
     const int n = lut->prm.n_depth;
     lut->max_span_px = 0;
+    std::vector<float> cmax(n, 0.0f);
+    {
+        int64_t *eo = nullptr;
+        float *cm = nullptr;
+        hipError_t e = hipMalloc((void **)&eo, sizeof(int64_t) * (n + 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&cm, sizeof(float) * n);
+        if (e == hipSuccess)
+            e = hipMemcpy(eo, lut->entry_off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            const int vt = lut->prm.value_dtype;
+            if (vt == CGH_F32) hipLaunchKernelGGL(plane_cmax_kernel<CGH_F32>, dim3(n), dim3(256), 0, 0, lut->values, eo, cm);
+            else if (vt == CGH_F16) hipLaunchKernelGGL(plane_cmax_kernel<CGH_F16>, dim3(n), dim3(256), 0, 0, lut->values, eo, cm);
+            else hipLaunchKernelGGL(plane_cmax_kernel<CGH_BF16>, dim3(n), dim3(256), 0, 0, lut->values, eo, cm);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpy(cmax.data(), cm, sizeof(float) * n, hipMemcpyDeviceToHost);
+        (void)hipFree(eo);
+        (void)hipFree(cm);
+        if (e != hipSuccess) return fail(CGH_EHIP, "plane bound: %s", hipGetErrorString(e));
+    }
     for (int d = 0; d < n; ++d) {
         DepthDesc &dd = lut->desc_host[d];
         const int nb = dd.nb;
@@ -415,6 +474,8 @@ int finish_lut(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
         dd.br1 = br1;
         dd.bc0 = bc0;
         dd.bc1 = bc1;
+        dd.cmax = cmax[d];
+        dd.pad = 0;
         if ((int64_t)bo[(int64_t)nb * nb] != lut->Nr[d])
             return fail(CGH_EHIP, "plane %d: selected %d entries, expected %lld", d,
                         bo[(int64_t)nb * nb], (long long)lut->Nr[d]);
@@ -441,6 +502,8 @@ int alloc_lut(wasabi_lut *lut)
         blk_total += (int64_t)dd.nb * dd.nb + 1;
     }
     lut->total_entries = lut->entry_off[n];
+    if (lut->total_entries >= INT64_C(2147483647))
+        return fail(CGH_EINVAL, "LUT of %lld entries exceeds 2^31 - 1", (long long)lut->total_entries);
     const size_t vb = value_bytes(lut->prm.value_dtype) * (size_t)std::max<int64_t>(lut->total_entries, 1);
     const size_t kb = sizeof(uint16_t) * (size_t)std::max<int64_t>(lut->total_entries, 1);
     const size_t bb = sizeof(int32_t) * (size_t)blk_total;

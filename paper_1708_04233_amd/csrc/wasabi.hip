@@ -27,7 +27,7 @@ namespace {
 
 constexpr int kT = 64;  // tile side, pixels
 constexpr int kThreads = 256;       // idwt workgroup
-constexpr int kTileThreads = 1024;  // superposition workgroup (16 waves; two fit a CU)
+constexpr int kTileThreads = 512;   // superposition workgroup (8 waves; four fit a CU)
 constexpr int MODE_PSI = 0, MODE_FUSED = 1;
 
 struct TileGeom {
@@ -59,52 +59,57 @@ __device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, i
 constexpr int kMaxLdsTiles = 4096;   // per-workgroup tile histograms live in LDS up to this
 constexpr int kDepthChunk = 8192;     // points per workgroup in the plane sort
 
-// ---- plane sort: points grouped by plane (invalid ones last), so that the per-tile lists built
-//      from them come out in plane order and concurrently running tiles share LUT planes in L2 ----
-// Also records the largest |a| of the valid points (bit pattern of a non-negative float, which
-// orders like its value) for the fixed-point scale of the superposition.
+// ---- point sort by (plane, row band): points grouped by plane and, within a plane, by 64-row band
+//      (invalid ones last).  Tile lists built from this order walk each plane's points by row, so
+//      at any moment the tiles read the same horizontal band of the plane's table: the table
+//      window row of a (tile, point) pair is tile_y - point_y + W/2, which then advances in step
+//      across all tiles, and the band stays in L2 while they use it. ----
+struct SortKey {
+    int n_depth;
+    int nyb;        // row bands per plane
+    int64_t y0;     // row of band 0 (window origin minus the largest half table)
+};
+
+__device__ inline int sort_key(const wasabi_point &p, const SortKey &k)
+{
+    if (p.depth < 0 || p.depth >= k.n_depth) return k.n_depth * k.nyb;
+    int64_t b = ((int64_t)p.y - k.y0) >> 6;
+    b = b < 0 ? 0 : (b >= k.nyb ? k.nyb - 1 : b);
+    return p.depth * k.nyb + (int)b;
+}
+
 template <bool LDS>
 __global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *pts, int64_t n,
-                                                           int n_depth, int32_t *counts,
-                                                           unsigned *amax)
+                                                           SortKey key, int32_t *counts)
 {
-    extern __shared__ int hist[];  // n_depth + 1 bins (LDS variant)
-    __shared__ unsigned wmax;
-    const int nbins = n_depth + 1;
-    if (threadIdx.x == 0) wmax = 0u;
-    if (LDS)
+    extern __shared__ int hist[];  // nbins (LDS variant)
+    const int nbins = key.n_depth * key.nyb + 1;
+    if (LDS) {
         for (int i = threadIdx.x; i < nbins; i += 1024) hist[i] = 0;
-    __syncthreads();
+        __syncthreads();
+    }
     const int64_t j0 = (int64_t)blockIdx.x * kDepthChunk;
     const int64_t j1 = min(n, j0 + kDepthChunk);
-    unsigned m = 0u;
     for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
-        const wasabi_point p = pts[j];
-        int d = p.depth;
-        if (d < 0 || d >= n_depth) {
-            d = n_depth;
-        } else {
-            m = max(m, __float_as_uint(fabsf(p.a)));
-        }
+        const int d = sort_key(pts[j], key);
         if (LDS) atomicAdd(&hist[d], 1);
         else atomicAdd(&counts[d], 1);
     }
-    atomicMax(&wmax, m);
-    __syncthreads();
-    if (threadIdx.x == 0) atomicMax(amax, wmax);
-    if (LDS)
+    if (LDS) {
+        __syncthreads();
         for (int i = threadIdx.x; i < nbins; i += 1024)
             if (hist[i]) atomicAdd(&counts[i], hist[i]);
+    }
 }
 
 template <bool LDS>
 __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point *pts, int64_t n,
-                                                             int n_depth,
+                                                             SortKey key,
                                                              unsigned long long *cursor,
                                                              wasabi_point *sorted)
 {
     extern __shared__ int sh[];  // LDS variant: local count[nbins] then base[nbins] (64-bit)
-    const int nbins = n_depth + 1;
+    const int nbins = key.n_depth * key.nyb + 1;
     int *cnt = sh;
     unsigned long long *base = (unsigned long long *)(sh + ((nbins + 1) & ~1));
     const int64_t j0 = (int64_t)blockIdx.x * kDepthChunk;
@@ -112,11 +117,7 @@ __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point 
     if (LDS) {
         for (int i = threadIdx.x; i < nbins; i += 1024) cnt[i] = 0;
         __syncthreads();
-        for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
-            int d = pts[j].depth;
-            if (d < 0 || d >= n_depth) d = n_depth;
-            atomicAdd(&cnt[d], 1);
-        }
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) atomicAdd(&cnt[sort_key(pts[j], key)], 1);
         __syncthreads();
         for (int i = threadIdx.x; i < nbins; i += 1024) {
             if (cnt[i]) base[i] = atomicAdd(&cursor[i], (unsigned long long)cnt[i]);
@@ -126,8 +127,7 @@ __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point 
     }
     for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
         const wasabi_point p = pts[j];
-        int d = p.depth;
-        if (d < 0 || d >= n_depth) d = n_depth;
+        const int d = sort_key(p, key);
         unsigned long long slot;
         if (LDS) slot = base[d] + (unsigned long long)atomicAdd(&cnt[d], 1);
         else slot = atomicAdd(&cursor[d], 1ull);
@@ -199,6 +199,62 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
             }
 }
 
+// Ordered lists: chunk w (64 consecutive sorted points) writes its per-tile counts to column w of a
+// tile-major matrix; the exclusive scan of that matrix gives each chunk its slice of every tile's
+// list, in chunk order.  Inside a chunk one wave takes the points one after another (lanes spread
+// over the point's tiles), so every tile's list keeps the sorted point order exactly.
+constexpr int kChunk = 64;
+
+__global__ __launch_bounds__(kChunk) void bin_count_matrix_kernel(const wasabi_point *pts, int64_t n,
+                                                                  const DepthDesc *desc, int n_depth,
+                                                                  int L, TileGeom g, int nwg,
+                                                                  int32_t *mat)
+{
+    __shared__ int hist[kMaxLdsTiles];
+    const int ntiles = g.ntx * g.nty;
+    for (int i = threadIdx.x; i < ntiles; i += kChunk) hist[i] = 0;
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    int ty0, ty1, tx0, tx1;
+    if (j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1))
+        for (int ty = ty0; ty < ty1; ++ty)
+            for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&hist[ty * g.ntx + tx], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ntiles; i += kChunk) mat[(int64_t)i * nwg + blockIdx.x] = hist[i];
+}
+
+__global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_point *pts, int64_t n,
+                                                                 const DepthDesc *desc, int n_depth,
+                                                                 int L, TileGeom g, int nwg,
+                                                                 const int64_t *moff, int32_t *list)
+{
+    __shared__ int cnt[kMaxLdsTiles];
+    const int ntiles = g.ntx * g.nty;
+    for (int i = threadIdx.x; i < ntiles; i += kChunk) cnt[i] = 0;
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * kChunk;
+    const int np = (int)min((int64_t)kChunk, n - j0);
+    for (int q = 0; q < np; ++q) {
+        const int64_t j = j0 + q;
+        int ty0, ty1, tx0, tx1;
+        if (!footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) continue;
+        const int w = tx1 - tx0, cells = (ty1 - ty0) * w;
+        for (int c = threadIdx.x; c < cells; c += kChunk) {
+            const int t = (ty0 + c / w) * g.ntx + tx0 + c % w;
+            const int rank = cnt[t];
+            cnt[t] = rank + 1;
+            list[moff[(int64_t)t * nwg + blockIdx.x] + rank] = (int32_t)j;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void gather_tile_off_kernel(const int64_t *moff, int64_t ntiles, int nwg, int64_t *off)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= ntiles) off[t] = moff[t * nwg];
+}
+
 // ---- exclusive scan of int32 counts into int64 offsets (n + 1 values) ----------------------
 __device__ inline int64_t block_incl_scan(int64_t v, int64_t *wave_sums, int64_t &total)
 {
@@ -266,7 +322,6 @@ struct TileArgs {
     const float2 *in;  // idwt: Mallat-layout field of the window (contiguous, row stride nx)
     float2 *out;       // MODE_PSI: Mallat field (row stride nx); otherwise pixels (row stride ld)
     int64_t ld;
-    const unsigned *amax;  // largest |a| of the points (float bits)
 };
 
 template <int L>
@@ -402,25 +457,17 @@ __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *ou
 
 // Fixed-point accumulation.  LDS float atomics are slow on this GPU, integer ones are not, so each
 // term a_j * c is formed exactly in FP64 (a product of two FP32 values), rounded once to the grid
-// 2^-s, and added as a 64-bit integer (ds_add_u64).  Integer sums are exact and independent of the
-// order of the adds.  The rounding uses the FP64 "magic number" 1.5 * 2^52: for |y| < 2^51,
-// bits(y + 1.5 * 2^52) - bits(1.5 * 2^52) is round-to-nearest-even(y) as an integer.
+// 2^-s, and added as a 32-bit integer (ds_add_u32).  Integer sums are exact and independent of the
+// order of the adds.  s is chosen per tile from the bound B_t = sum_j |a_j| max|c|_plane(j) over
+// the tile's points (each point adds at most one term to any coefficient): with B_t < 2^e and
+// s = 30 - e, every scaled partial and final sum stays below 2^31 in magnitude.  Rounding uses the
+// FP64 "magic number" 1.5 * 2^52: for |y| < 2^31 the low 32 bits of y + 1.5 * 2^52 are
+// round-to-nearest-even(y) in two's complement.
 constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
-constexpr long long kMagicBits = 0x4338000000000000LL;
 
-__device__ inline long long to_fixed(float v, double scaled_amp)
+__device__ inline int to_fixed(float v, double scaled_amp)
 {
-    return __double_as_longlong(fma((double)v, scaled_amp, kMagic)) - kMagicBits;
-}
-
-// Scale exponent s: every term satisfies |a c| <= 2^e * 2^L with 2^e >= max|a| (e >= 0), so
-// |term| * 2^s < 2^40 keeps the rounding exact-range (< 2^51) and a coefficient's sum below 2^63
-// unless more than 2^22 terms pile up on it coherently.
-__device__ inline int fixed_shift(unsigned amax_bits, int L)
-{
-    const int E = (int)((amax_bits >> 23) & 255) - 127;  // max|a| < 2^(E+1)
-    const int e = max(0, E + 1);
-    return 40 - L - e;
+    return __double2loint(fma((double)v, scaled_amp, kMagic));
 }
 
 // Adds the kept coefficients of one (tile, point) pair into the tile's LDS accumulators.  Called by
@@ -429,9 +476,9 @@ __device__ inline int fixed_shift(unsigned amax_bits, int L)
 // r) and land at LDS element dst0 + r * ROW + key.  Each row is walked U x 64 entries at a time
 // with all loads issued before the LDS adds.
 template <int L, int VT>
-__device__ inline void add_pair(long long *are, long long *aim, const void *values,
-                                const uint16_t *keys, int eb, int dst0, int nrows,
-                                double scaled_amp, int rstart, int rcount)
+__device__ inline void add_pair(int *are, int *aim, const void *values, const uint16_t *keys,
+                                int eb, int dst0, int nrows, double scaled_amp, int rstart,
+                                int rcount)
 {
     using S = TileShape<L>;
     constexpr int U = 4;
@@ -458,8 +505,8 @@ __device__ inline void add_pair(long long *are, long long *aim, const void *valu
                 const int e = c + 64 * u + lane;
                 if (e < rc) {
                     const int at = d + k[u];
-                    atomicAdd((unsigned long long *)&are[at], (unsigned long long)to_fixed(v[u].x, scaled_amp));
-                    atomicAdd((unsigned long long *)&aim[at], (unsigned long long)to_fixed(v[u].y, scaled_amp));
+                    atomicAdd(&are[at], to_fixed(v[u].x, scaled_amp));
+                    atomicAdd(&aim[at], to_fixed(v[u].y, scaled_amp));
                 }
             }
         }
@@ -471,19 +518,33 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
 {
     using S = TileShape<L>;
     constexpr int NW = kTileThreads / 64;
-    __shared__ long long acc[2 * S::N];  // fixed-point re plane, then im plane
-    long long *are = acc, *aim = acc + S::N;
+    __shared__ int acc[2 * S::N];  // fixed-point re plane, then im plane
+    __shared__ double red[kTileThreads / 64];
+    int *are = acc, *aim = acc + S::N;
     const int tile = blockIdx.x;
     const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int tbh = th >> L, tbw = tw >> L;
-    for (int i = threadIdx.x; i < 2 * S::N; i += kTileThreads) acc[i] = 0;
-    const int shift = fixed_shift(*a.amax, L);
-    __syncthreads();
-
+    const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
+
+    // bound of every coefficient of this tile -> fixed-point scale 2^shift
+    double bound = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
+        const wasabi_point pt = a.pts[a.tile_pts[p]];
+        bound += (double)fabsf(pt.a) * (double)a.desc[pt.depth].cmax;
+    }
+    for (int o = 32; o > 0; o >>= 1) bound += __shfl_down(bound, o);
+    if (lane == 0) red[wave] = bound;
+    for (int i = threadIdx.x; i < 2 * S::N; i += kTileThreads) acc[i] = 0;
+    __syncthreads();
+    bound = 0.0;
+    for (int w = 0; w < NW; ++w) bound += red[w];
+    int ex;
+    (void)frexp(bound * (1.0 + 1e-6) + 1e-300, &ex);  // bound < 2^ex
+    const int shift = min(30 - ex, 1000);
+
     const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
     // Waves take interleaved pairs (wave w: pairs w, w + NW, ...), so the waves of a tile work
     // on neighbouring list positions, i.e. on the same LUT planes.  Each wave gathers the
@@ -547,27 +608,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     }
     __syncthreads();
 
-    // fixed point -> FP32, in place: the float planes occupy the first half of `acc`
-    constexpr int PER = (S::N + kTileThreads - 1) / kTileThreads;
+    // fixed point -> FP32 in place (each element converts itself)
     const double unscale = ldexp(1.0, -shift);
-    float fr[PER], fi[PER];
-#pragma unroll
-    for (int k2 = 0; k2 < PER; ++k2) {
-        const int i = threadIdx.x + k2 * kTileThreads;
-        if (i < S::N) {
-            fr[k2] = (float)((double)are[i] * unscale);
-            fi[k2] = (float)((double)aim[i] * unscale);
-        }
-    }
-    __syncthreads();
-    float *sre = (float *)acc, *sim = sre + S::N;
-#pragma unroll
-    for (int k2 = 0; k2 < PER; ++k2) {
-        const int i = threadIdx.x + k2 * kTileThreads;
-        if (i < S::N) {
-            sre[i] = fr[k2];
-            sim[i] = fi[k2];
-        }
+    float *sre = (float *)are, *sim = (float *)aim;
+    for (int i = threadIdx.x; i < S::N; i += kTileThreads) {
+        sre[i] = (float)((double)are[i] * unscale);
+        sim[i] = (float)((double)aim[i] * unscale);
     }
     __syncthreads();
 
@@ -635,14 +681,19 @@ int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc,
 // Plane-sort the points and build the per-tile point lists; results live in `sc`.
 int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,
                Scratch &sc, hipStream_t s, const wasabi_point **sorted_out,
-               int64_t **tile_off_out, int32_t **tile_pts_out, const unsigned **amax_out)
+               int64_t **tile_off_out, int32_t **tile_pts_out)
 {
     const int64_t ntiles = (int64_t)g.ntx * g.nty;
     const int64_t per_side = (lut->max_span_px + kT - 1) / kT + 1;
     const int64_t per_point = std::min<int64_t>(per_side * per_side, ntiles);
     const int64_t bound = std::max<int64_t>(n * per_point, 1);
     const int nd = lut->prm.n_depth, L = lut->L;
-    const int nbins = nd + 1;
+    SortKey key;
+    key.n_depth = nd;
+    key.y0 = g.oy - lut->max_span_px;
+    key.nyb = (int)std::min<int64_t>(((int64_t)g.ny + 2 * lut->max_span_px + 63) / 64, 4096);
+    if ((int64_t)key.nyb * nd + 1 > (INT64_C(1) << 26)) key.nyb = std::max(1, (1 << 26) / nd - 1);
+    const int nbins = nd * key.nyb + 1;
     int32_t *counts, *dcounts;
     int64_t *off, *doff;
     unsigned long long *cursor, *dcursor;
@@ -657,19 +708,16 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     if ((rc = sc.alloc((void **)&doff, sizeof(int64_t) * (nbins + 1)))) return rc;
     if ((rc = sc.alloc((void **)&dcursor, sizeof(unsigned long long) * nbins))) return rc;
     if ((rc = sc.alloc((void **)&sorted, sizeof(wasabi_point) * std::max<int64_t>(n, 1)))) return rc;
-    unsigned *amax;
-    if ((rc = sc.alloc((void **)&amax, sizeof(unsigned)))) return rc;
     ProfScope prof("bin", s);
     // plane sort
     CGH_TRY_HIP(hipMemsetAsync(dcounts, 0, sizeof(int32_t) * nbins, s));
-    CGH_TRY_HIP(hipMemsetAsync(amax, 0, sizeof(unsigned), s));
     const bool lds_depth = nbins <= 4096;
     const unsigned dgrid = (unsigned)std::max<int64_t>((n + kDepthChunk - 1) / kDepthChunk, 1);
     if (n > 0) {
         if (lds_depth)
-            hipLaunchKernelGGL(depth_count_kernel<true>, dim3(dgrid), dim3(1024), sizeof(int) * nbins, s, pts, n, nd, dcounts, amax);
+            hipLaunchKernelGGL(depth_count_kernel<true>, dim3(dgrid), dim3(1024), sizeof(int) * nbins, s, pts, n, key, dcounts);
         else
-            hipLaunchKernelGGL(depth_count_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, nd, dcounts, amax);
+            hipLaunchKernelGGL(depth_count_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dcounts);
         CGH_CHECK_LAUNCH("depth_count_kernel");
     }
     if ((rc = scan_counts(dcounts, nbins, doff, sc, s))) return rc;
@@ -677,35 +725,49 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
         CGH_TRY_HIP(hipMemcpyAsync(dcursor, doff, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
         const size_t sh = sizeof(int) * ((nbins + 1) & ~1) + sizeof(unsigned long long) * nbins;
         if (lds_depth)
-            hipLaunchKernelGGL(depth_scatter_kernel<true>, dim3(dgrid), dim3(1024), sh, s, pts, n, nd, dcursor, sorted);
+            hipLaunchKernelGGL(depth_scatter_kernel<true>, dim3(dgrid), dim3(1024), sh, s, pts, n, key, dcursor, sorted);
         else
-            hipLaunchKernelGGL(depth_scatter_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, nd, dcursor, sorted);
+            hipLaunchKernelGGL(depth_scatter_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dcursor, sorted);
         CGH_CHECK_LAUNCH("depth_scatter_kernel");
     }
-    // tile lists over the plane-sorted points
-    CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
-    const bool lds_tiles = ntiles <= kMaxLdsTiles;
+    // tile lists over the sorted points
+    const int64_t nwg = (n + kChunk - 1) / kChunk;
     const unsigned pblocks = (unsigned)((n + 255) / 256);
-    if (n > 0) {
-        if (lds_tiles)
-            hipLaunchKernelGGL(bin_count_kernel<true>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, counts);
-        else
-            hipLaunchKernelGGL(bin_count_kernel<false>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, counts);
-        CGH_CHECK_LAUNCH("bin_count_kernel");
-    }
-    if ((rc = scan_counts(counts, ntiles, off, sc, s))) return rc;
-    if (n > 0) {
-        CGH_TRY_HIP(hipMemcpyAsync(cursor, off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToDevice, s));
-        if (lds_tiles)
-            hipLaunchKernelGGL(bin_fill_kernel<true>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, cursor, list);
-        else
-            hipLaunchKernelGGL(bin_fill_kernel<false>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, cursor, list);
-        CGH_CHECK_LAUNCH("bin_fill_kernel");
+    if (n > 0 && ntiles <= kMaxLdsTiles && nwg * ntiles <= (INT64_C(1) << 24)) {
+        int32_t *mat;
+        int64_t *moff;
+        if ((rc = sc.alloc((void **)&mat, sizeof(int32_t) * nwg * ntiles))) return rc;
+        if ((rc = sc.alloc((void **)&moff, sizeof(int64_t) * (nwg * ntiles + 1)))) return rc;
+        hipLaunchKernelGGL(bin_count_matrix_kernel, dim3((unsigned)nwg), dim3(kChunk), 0, s, sorted, n, lut->desc, nd, L, g, (int)nwg, mat);
+        CGH_CHECK_LAUNCH("bin_count_matrix_kernel");
+        if ((rc = scan_counts(mat, nwg * ntiles, moff, sc, s))) return rc;
+        hipLaunchKernelGGL(gather_tile_off_kernel, dim3((unsigned)((ntiles + 256) / 256)), dim3(256), 0, s, moff, ntiles, (int)nwg, off);
+        CGH_CHECK_LAUNCH("gather_tile_off_kernel");
+        hipLaunchKernelGGL(bin_fill_matrix_kernel, dim3((unsigned)nwg), dim3(kChunk), 0, s, sorted, n, lut->desc, nd, L, g, (int)nwg, moff, list);
+        CGH_CHECK_LAUNCH("bin_fill_matrix_kernel");
+    } else {
+        CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
+        const bool lds_tiles = ntiles <= kMaxLdsTiles;
+        if (n > 0) {
+            if (lds_tiles)
+                hipLaunchKernelGGL(bin_count_kernel<true>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, counts);
+            else
+                hipLaunchKernelGGL(bin_count_kernel<false>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, counts);
+            CGH_CHECK_LAUNCH("bin_count_kernel");
+        }
+        if ((rc = scan_counts(counts, ntiles, off, sc, s))) return rc;
+        if (n > 0) {
+            CGH_TRY_HIP(hipMemcpyAsync(cursor, off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToDevice, s));
+            if (lds_tiles)
+                hipLaunchKernelGGL(bin_fill_kernel<true>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, cursor, list);
+            else
+                hipLaunchKernelGGL(bin_fill_kernel<false>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, cursor, list);
+            CGH_CHECK_LAUNCH("bin_fill_kernel");
+        }
     }
     *sorted_out = sorted;
     *tile_off_out = off;
     *tile_pts_out = list;
-    *amax_out = amax;
     return CGH_OK;
 }
 
@@ -751,7 +813,6 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.in = nullptr;
     a.out = out;
     a.ld = ld;
-    a.amax = nullptr;
     return a;
 }
 
@@ -766,11 +827,9 @@ int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, in
     int64_t *tile_off;
     int32_t *tile_pts;
     const wasabi_point *sorted;
-    const unsigned *amax;
-    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts, &amax);
+    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts);
     if (rc) return rc;
-    TileArgs a = make_args(lut, sorted, tile_off, tile_pts, g, (float2 *)out, ld);
-    a.amax = amax;
+    const TileArgs a = make_args(lut, sorted, tile_off, tile_pts, g, (float2 *)out, ld);
     if (mode == MODE_PSI) return launch_tile<MODE_PSI>(lut->L, lut->prm.value_dtype, a, s);
     return launch_tile<MODE_FUSED>(lut->L, lut->prm.value_dtype, a, s);
 }
