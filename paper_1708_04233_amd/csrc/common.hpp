@@ -74,6 +74,11 @@ class ProfScope {
 // blk_off[d] holds nb*nb + 1 offsets: entries of block (br, bc) are [blk_off[br*nb+bc],
 // blk_off[br*nb+bc+1]) relative to the plane's first entry.
 // ---------------------------------------------------------------------------------------------
+// Selectivity from which a LUT also gets the dense layout (and the superposition uses it): at
+// gamma ~ 0.35 and above most codes of an occupied block are kept, so whole blocks cost about as
+// many bytes as (value, key) entries and need no keys, no LDS atomics and no fixed point.
+constexpr double kDenseGamma = 0.35;
+
 __host__ __device__ constexpr int block_stride(int L)
 {
     return (1 << (2 * L)) + ((1 << L) <= 16 ? (1 << L) : 0);
@@ -88,6 +93,17 @@ struct DepthDesc {
     int32_t pad;
     int64_t entry_base;   // first entry of the plane in values/keys
     int64_t blkoff_base;  // first element of the plane's blk_off array
+    int64_t dense_base;   // dense layout: first coefficient of the plane in dense values
+    int64_t rows_base;    // dense layout: first DenseRow of the plane (nb rows)
+};
+
+// Dense layout (kept when gamma is large): every Haar block of a block row between the first and
+// the last block holding kept entries is stored whole (B*B coefficients, zeros where dropped),
+// block after block, so the blocks a tile needs from one table block row are one contiguous run.
+struct DenseRow {
+    int32_t lo, hi;  // stored blocks [lo, hi) of this block row
+    int32_t off;     // first coefficient of block lo, relative to the plane's dense_base
+    int32_t pad;
 };
 
 }  // namespace cgh
@@ -107,6 +123,9 @@ struct wasabi_lut {
     int32_t *blk_off;                 // device
     void *values;                     // device: float2 (F32) or uint32 packed pair (F16, BF16)
     uint16_t *keys;                   // device
+    bool dense;                       // dense layout present (used by the superposition)
+    void *dense_values;               // device, same element type as values
+    cgh::DenseRow *dense_rows;        // device
     size_t device_bytes;
 };
 

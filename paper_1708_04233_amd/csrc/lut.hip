@@ -374,6 +374,29 @@ __global__ __launch_bounds__(256) void plane_cmax_kernel(const void *values, con
     if (threadIdx.x == 0) cmax[blockIdx.x] = red[0];
 }
 
+// ---- dense layout: scatter the kept entries of one table block row into its whole blocks ------
+struct DenseJob {
+    int64_t entry_base, blkoff_base, dense_base;
+    int32_t nb, br, lo, hi, off, pad;
+};
+
+__global__ __launch_bounds__(256) void dense_scatter_kernel(const DenseJob *jobs, int L, int vbytes,
+                                                            const int32_t *blk_off, const uint16_t *keys,
+                                                            const void *values, void *dense)
+{
+    const DenseJob j = jobs[blockIdx.x];
+    const int BB = 1 << (2 * L), BS = block_stride(L);
+    const int32_t *bo = blk_off + j.blkoff_base + (int64_t)j.br * j.nb;
+    const int32_t e0 = bo[j.lo], e1 = bo[j.hi];
+    for (int32_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const int key = keys[j.entry_base + e];
+        const int bcol = key / BS, code = key - (key / BS) * BS;
+        const int64_t at = j.dense_base + j.off + (int64_t)(bcol - j.lo) * BB + code;
+        if (vbytes == 8) ((float2 *)dense)[at] = ((const float2 *)values)[j.entry_base + e];
+        else ((uint32_t *)dense)[at] = ((const uint32_t *)values)[j.entry_base + e];
+    }
+}
+
 // ---- quantisation ---------------------------------------------------------------------------
 __global__ void quantize_kernel(const double4 *pts, int64_t n, double pitch, double z_min,
                                 double z_max, double dz, int n_depth, int L, wasabi_point *out)
@@ -429,6 +452,80 @@ void flat_to_block(int64_t flat, int W, int L, int &br, int &bc, int &code)
 
 size_t value_bytes(int vt) { return vt == CGH_F32 ? 8 : 4; }
 
+// Dense layout for large gamma: row spans from the block offsets, then a scatter kernel.
+int build_dense(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
+{
+    const int n = lut->prm.n_depth, B = lut->B, BB = B * B;
+    lut->dense = lut->prm.gamma >= kDenseGamma;
+    if (!lut->dense) return CGH_OK;
+    std::vector<DenseRow> rows;
+    std::vector<DenseJob> jobs;
+    int64_t total = 0;
+    for (int d = 0; d < n; ++d) {
+        DepthDesc &dd = lut->desc_host[d];
+        const int nb = dd.nb;
+        const int32_t *bo = blk_off_host.data() + dd.blkoff_base;
+        dd.dense_base = total;
+        dd.rows_base = (int64_t)rows.size();
+        int64_t off = 0;
+        for (int br = 0; br < nb; ++br) {
+            int lo = nb, hi = 0;
+            for (int bc = 0; bc < nb; ++bc)
+                if (bo[br * nb + bc + 1] > bo[br * nb + bc]) {
+                    lo = std::min(lo, bc);
+                    hi = bc + 1;
+                }
+            if (hi <= lo) lo = hi = 0;
+            DenseRow r;
+            r.lo = lo;
+            r.hi = hi;
+            r.off = (int32_t)off;
+            r.pad = 0;
+            rows.push_back(r);
+            if (hi > lo) {
+                DenseJob j;
+                j.entry_base = dd.entry_base;
+                j.blkoff_base = dd.blkoff_base;
+                j.dense_base = total;
+                j.nb = nb;
+                j.br = br;
+                j.lo = lo;
+                j.hi = hi;
+                j.off = (int32_t)off;
+                j.pad = 0;
+                jobs.push_back(j);
+            }
+            off += (int64_t)(hi - lo) * BB;
+        }
+        if (off >= INT32_MAX) return fail(CGH_EINVAL, "plane %d: dense table too large", d);
+        total += off;
+    }
+    const size_t vb = value_bytes(lut->prm.value_dtype);
+    hipError_t e1 = hipMalloc(&lut->dense_values, vb * (size_t)std::max<int64_t>(total, 1));
+    hipError_t e2 = hipMalloc((void **)&lut->dense_rows, sizeof(DenseRow) * rows.size());
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CGH_ENOMEM, "dense LUT allocation of %lld coefficients failed", (long long)total);
+    }
+    lut->device_bytes += vb * (size_t)total + sizeof(DenseRow) * rows.size();
+    CGH_TRY_HIP(hipMemset(lut->dense_values, 0, vb * (size_t)std::max<int64_t>(total, 1)));
+    CGH_TRY_HIP(hipMemcpy(lut->dense_rows, rows.data(), sizeof(DenseRow) * rows.size(), hipMemcpyHostToDevice));
+    if (!jobs.empty()) {
+        DenseJob *jd = nullptr;
+        CGH_TRY_HIP(hipMalloc((void **)&jd, sizeof(DenseJob) * jobs.size()));
+        hipError_t e = hipMemcpy(jd, jobs.data(), sizeof(DenseJob) * jobs.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(dense_scatter_kernel, dim3((unsigned)jobs.size()), dim3(256), 0, 0, jd,
+                               lut->L, (int)vb, lut->blk_off, lut->keys, lut->values, lut->dense_values);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        (void)hipFree(jd);
+        if (e != hipSuccess) return fail(CGH_EHIP, "dense LUT: %s", hipGetErrorString(e));
+    }
+    return CGH_OK;
+}
+
 // Fill the occupied block ranges, the per-plane value bound and the device descriptors.
 int finish_lut(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
 {
@@ -481,6 +578,8 @@ int finish_lut(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
                         bo[(int64_t)nb * nb], (long long)lut->Nr[d]);
         lut->max_span_px = std::max(lut->max_span_px, std::max(br1 - br0, bc1 - bc0) * lut->B);
     }
+    int rc = build_dense(lut, blk_off_host);
+    if (rc) return rc;
     CGH_TRY_HIP(hipMemcpy(lut->desc, lut->desc_host.data(), sizeof(DepthDesc) * n, hipMemcpyHostToDevice));
     return CGH_OK;
 }
@@ -499,6 +598,8 @@ int alloc_lut(wasabi_lut *lut)
         dd.nb = lut->W[d] / lut->B;
         dd.entry_base = lut->entry_off[d];
         dd.blkoff_base = blk_total;
+        dd.dense_base = 0;
+        dd.rows_base = 0;
         blk_total += (int64_t)dd.nb * dd.nb + 1;
     }
     lut->total_entries = lut->entry_off[n];
@@ -530,6 +631,9 @@ wasabi_lut *new_lut(const wasabi_lut_params *prm)
     lut->blk_off = nullptr;
     lut->values = nullptr;
     lut->keys = nullptr;
+    lut->dense = false;
+    lut->dense_values = nullptr;
+    lut->dense_rows = nullptr;
     lut->device_bytes = 0;
     lut->total_entries = 0;
     lut->max_span_px = 0;
@@ -832,6 +936,8 @@ extern "C" void wasabi_lut_free(wasabi_lut *lut)
     (void)hipFree(lut->blk_off);
     (void)hipFree(lut->values);
     (void)hipFree(lut->keys);
+    (void)hipFree(lut->dense_values);
+    (void)hipFree(lut->dense_rows);
     delete lut;
 }
 

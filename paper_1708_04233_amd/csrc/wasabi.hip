@@ -19,6 +19,7 @@
 // MODE_FUSED inverts each block in LDS and writes pixels, so the wavelet field never reaches HBM.
 // idwt_kernel gathers a tile from a Mallat-layout field, inverts it in LDS and writes pixels.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.hpp"
 
@@ -322,6 +323,11 @@ struct TileArgs {
     const float2 *in;  // idwt: Mallat-layout field of the window (contiguous, row stride nx)
     float2 *out;       // MODE_PSI: Mallat field (row stride nx); otherwise pixels (row stride ld)
     int64_t ld;
+    const void *dense;          // dense layout values (or NULL)
+    const DenseRow *dense_rows; // dense layout block-row spans
+    int n_depth;
+    int *plane_done;            // plane pacing: tiles that finished plane d (NULL = off)
+    int pace_slack;             // a tile starts plane d once all tiles finished plane d - slack
 };
 
 template <int L>
@@ -624,6 +630,207 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     }
 }
 
+// Dense-layout superposition.  Wave w of the tile's 8 waves owns the 512 coefficients
+// [512 w, 512 w + 512) of the tile (block-major order, i.e. block row w for L = 3) and keeps them in
+// FP32 registers, lane = code: for every point of the tile (in list order) it reads the table
+// blocks that fall on its coefficients -- a contiguous run per table block row -- and does
+// acc += a_j * c.  No LDS traffic, no atomics; every coefficient is summed in list order.
+constexpr int kDenseThreads = 512;
+constexpr int kPaceSpin = 20000;       // ~ a few ms of polling at most, then pacing is dropped
+constexpr int kPaceMaxPlanes = 4096;  // plane bounds live in the tile's LDS staging buffer
+constexpr int kPaceCounters = 64;     // counter words per plane
+
+template <int L, int VT, int MODE>
+__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void dense_tile_kernel(TileArgs a)
+{
+    using S = TileShape<L>;
+    constexpr int BB = S::B * S::B;
+    constexpr int NW = kDenseThreads / 64;
+    constexpr int PER = kT * kT / kDenseThreads;  // coefficients per lane (8)
+    __shared__ float sbuf[2 * S::N];
+    const int tile = blockIdx.x;
+    const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
+    const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
+    const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
+
+    // the lane's coefficients: c_i = 512 w + 64 i + lane -> tile block b_i = c_i / BB, code_i
+    int tbr[PER], tbc[PER], code[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int c = wave * 512 + i * 64 + lane;
+        const int b = c / BB;
+        tbr[i] = b / S::TB;
+        tbc[i] = b % S::TB;
+        code[i] = c % BB;
+    }
+    float are[PER], aim[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) are[i] = aim[i] = 0.0f;
+
+    if (BB >= 64) {
+        // For L >= 3 the wave's coefficients lie in one tile block row (tr) and tile block columns
+        // tbc[i]; per pair only one table block row (tr - obr) is involved.  Lane k resolves pair k
+        // of each 64-pair batch up to the address of its first coefficient (one parallel pass over
+        // the dependent loads), then the wave walks the pairs.
+        const int tr = tbr[0];
+        auto run = [&](int64_t q0, int64_t q1) {
+            for (int64_t pb = q0; pb < q1; pb += 64) {
+                const int64_t pk = pb + lane;
+                int m_clo = 0, m_chi = 0;  // tile block columns [clo, chi) the pair covers
+                int m_blo = 0, m_bhi = 0;  // address of tile block column 0 (64-bit, split)
+                float m_amp = 0.0f;
+                if (pk < q1) {
+                    const wasabi_point pt = a.pts[a.tile_pts[pk]];
+                    const DepthDesc dd = a.desc[pt.depth];
+                    const int64_t xg = (int64_t)(pt.x >> L) << L, yg = (int64_t)(pt.y >> L) << L;
+                    const int obr = (int)((yg - dd.W / 2 - gy0) >> L);
+                    const int obc = (int)((xg - dd.W / 2 - gx0) >> L);
+                    const int br = tr - obr;
+                    if (br >= dd.br0 && br < dd.br1) {
+                        const DenseRow row = a.dense_rows[dd.rows_base + br];
+                        m_clo = max(row.lo + obc, 0);
+                        m_chi = min(row.hi + obc, S::TB);
+                        const int64_t b0 = dd.dense_base + row.off - (int64_t)(row.lo + obc) * BB;
+                        m_blo = (int)(b0 & 0xffffffff);
+                        m_bhi = (int)(b0 >> 32);
+                        m_amp = pt.a;
+                    }
+                }
+                const int cnt = (int)min((int64_t)64, q1 - pb);
+                for (int k = 0; k < cnt; ++k) {
+                    const int clo = __builtin_amdgcn_readlane(m_clo, k), chi = __builtin_amdgcn_readlane(m_chi, k);
+                    if (chi <= clo) continue;
+                    const int64_t b0 = ((int64_t)__builtin_amdgcn_readlane(m_bhi, k) << 32) | (uint32_t)__builtin_amdgcn_readlane(m_blo, k);
+                    const float amp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k));
+                    float2 v[PER];
+#pragma unroll
+                    for (int i = 0; i < PER; ++i)
+                        if (tbc[i] >= clo && tbc[i] < chi) v[i] = load_value<VT>(a.dense, b0 + (int64_t)tbc[i] * BB + code[i]);
+#pragma unroll
+                    for (int i = 0; i < PER; ++i)
+                        if (tbc[i] >= clo && tbc[i] < chi) {
+                            are[i] = fmaf(amp, v[i].x, are[i]);
+                            aim[i] = fmaf(amp, v[i].y, aim[i]);
+                        }
+                }
+            }
+        };
+        if (a.plane_done == nullptr) {
+            run(p0, p1);
+        } else {
+            // Plane pacing.  The tile's list is in plane order; all resident tiles walk the planes
+            // together (a tile starts plane d only after every tile finished plane d - slack), so
+            // the table bands being read at any moment stay in L2.  Every wait is bounded: after
+            // kPaceSpin polls a tile stops waiting for good, so progress never depends on it.
+            int *bnd = (int *)sbuf;  // plane d owns list positions [bnd[d], bnd[d + 1])
+            const int nd = a.n_depth;
+            for (int d = threadIdx.x; d <= nd; d += kDenseThreads) bnd[d] = 0;
+            __syncthreads();
+            for (int64_t p = p0 + threadIdx.x; p < p1; p += kDenseThreads) {
+                const int d = a.pts[a.tile_pts[p]].depth;
+                const int dn = (p + 1 < p1) ? a.pts[a.tile_pts[p + 1]].depth : nd;
+                for (int e = d + 1; e <= dn; ++e) bnd[e] = (int)(p + 1 - p0);  // ends of planes d..dn-1
+            }
+            __syncthreads();
+            // planes before the first one present start at 0; fill the gaps forward
+            if (threadIdx.x == 0) {
+                int last = 0;
+                for (int d = 0; d <= nd; ++d) {
+                    if (bnd[d] < last) bnd[d] = last;
+                    last = bnd[d];
+                }
+            }
+            __syncthreads();
+            // plane d's counter is spread over kPaceCounters words (tile t counts into word t % 64),
+            // so the 64 lanes of wave 0 poll them in parallel and no word sees more than a few adds
+            bool pacing = true;
+            const int ntiles = a.g.ntx * a.g.nty;
+            const int my_word = tile % kPaceCounters;
+            const int want = ntiles / kPaceCounters + (lane < ntiles % kPaceCounters ? 1 : 0);
+            __shared__ int s_go;
+            for (int d = 0; d < nd; ++d) {
+                const int64_t q0 = p0 + bnd[d], q1 = p0 + bnd[d + 1];
+                if (pacing && d >= a.pace_slack) {
+                    if (wave == 0) {
+                        const int *w = a.plane_done + (int64_t)(d - a.pace_slack) * kPaceCounters + lane;
+                        int it = 0;
+                        while (it < kPaceSpin) {
+                            const bool ok = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
+                            if (__ballot(!ok) == 0) break;
+                            __builtin_amdgcn_s_sleep(2);
+                            ++it;
+                        }
+                        if (lane == 0) s_go = it < kPaceSpin;
+                    }
+                    __syncthreads();
+                    pacing = s_go != 0;
+                }
+                if (q1 > q0) run(q0, q1);
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_fetch_add(a.plane_done + (int64_t)d * kPaceCounters + my_word, 1,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int64_t pb = p0; pb < p1; pb += 64) {
+            const int64_t pk = pb + lane;
+            int m_d = 0, m_obr = 0, m_obc = 0;
+            float m_amp = 0.0f;
+            if (pk < p1) {
+                const wasabi_point pt = a.pts[a.tile_pts[pk]];
+                const int W = a.desc[pt.depth].W;
+                const int64_t xg = (int64_t)(pt.x >> L) << L, yg = (int64_t)(pt.y >> L) << L;
+                m_d = pt.depth;
+                m_obr = (int)((yg - W / 2 - gy0) >> L);
+                m_obc = (int)((xg - W / 2 - gx0) >> L);
+                m_amp = pt.a;
+            }
+            const int cnt = (int)min((int64_t)64, p1 - pb);
+            for (int k = 0; k < cnt; ++k) {
+                const int d = __builtin_amdgcn_readlane(m_d, k);
+                const int obr = __builtin_amdgcn_readlane(m_obr, k);
+                const int obc = __builtin_amdgcn_readlane(m_obc, k);
+                const float amp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k));
+                const DepthDesc &dd = a.desc[d];
+                const int64_t base = dd.dense_base;
+                const DenseRow *rows = a.dense_rows + dd.rows_base;
+#pragma unroll
+                for (int i = 0; i < PER; ++i) {
+                    const int br = tbr[i] - obr, bc = tbc[i] - obc;
+                    if (br < dd.br0 || br >= dd.br1) continue;
+                    const DenseRow row = rows[br];
+                    if (bc < row.lo || bc >= row.hi) continue;
+                    const float2 v = load_value<VT>(a.dense, base + row.off + (int64_t)(bc - row.lo) * BB + code[i]);
+                    are[i] = fmaf(amp, v.x, are[i]);
+                    aim[i] = fmaf(amp, v.y, aim[i]);
+                }
+            }
+        }
+    }
+
+    // registers -> LDS (tile block layout) -> inverse or Mallat output
+    float *sre = sbuf, *sim = sbuf + S::N;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int at = tbr[i] * S::ROW + tbc[i] * S::BS + code[i];
+        sre[at] = are[i];
+        sim[at] = aim[i];
+    }
+    __syncthreads();
+    if (MODE == MODE_PSI) {
+        tile_mallat_io<L, false, kDenseThreads>(sre, sim, a.out, a.g, ty, tx, th, tw);
+    } else {
+        tile_inverse_and_store<L, kDenseThreads>(sre, sim, a.out, a.ld, ty, tx, th, tw);
+    }
+    (void)NW;
+}
+
 template <int L>
 __global__ __launch_bounds__(kThreads) void idwt_kernel(TileArgs a)
 {
@@ -681,7 +888,7 @@ int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc,
 // Plane-sort the points and build the per-tile point lists; results live in `sc`.
 int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,
                Scratch &sc, hipStream_t s, const wasabi_point **sorted_out,
-               int64_t **tile_off_out, int32_t **tile_pts_out)
+               int64_t **tile_off_out, int32_t **tile_pts_out, bool *ordered_out)
 {
     const int64_t ntiles = (int64_t)g.ntx * g.nty;
     const int64_t per_side = (lut->max_span_px + kT - 1) / kT + 1;
@@ -733,7 +940,9 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     // tile lists over the sorted points
     const int64_t nwg = (n + kChunk - 1) / kChunk;
     const unsigned pblocks = (unsigned)((n + 255) / 256);
+    *ordered_out = false;
     if (n > 0 && ntiles <= kMaxLdsTiles && nwg * ntiles <= (INT64_C(1) << 24)) {
+        *ordered_out = true;
         int32_t *mat;
         int64_t *moff;
         if ((rc = sc.alloc((void **)&mat, sizeof(int32_t) * nwg * ntiles))) return rc;
@@ -772,8 +981,20 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
 }
 
 template <int L, int MODE>
+void launch_dense_l(int vt, const TileArgs &a, unsigned grid, hipStream_t s)
+{
+    if (vt == CGH_F32) hipLaunchKernelGGL((dense_tile_kernel<L, CGH_F32, MODE>), dim3(grid), dim3(kDenseThreads), 0, s, a);
+    else if (vt == CGH_F16) hipLaunchKernelGGL((dense_tile_kernel<L, CGH_F16, MODE>), dim3(grid), dim3(kDenseThreads), 0, s, a);
+    else hipLaunchKernelGGL((dense_tile_kernel<L, CGH_BF16, MODE>), dim3(grid), dim3(kDenseThreads), 0, s, a);
+}
+
+template <int L, int MODE>
 void launch_tile_l(int vt, const TileArgs &a, unsigned grid, hipStream_t s)
 {
+    if (a.dense) {
+        launch_dense_l<L, MODE>(vt, a, grid, s);
+        return;
+    }
     if (vt == CGH_F32) hipLaunchKernelGGL((tile_kernel<L, CGH_F32, MODE>), dim3(grid), dim3(kTileThreads), 0, s, a);
     else if (vt == CGH_F16) hipLaunchKernelGGL((tile_kernel<L, CGH_F16, MODE>), dim3(grid), dim3(kTileThreads), 0, s, a);
     else hipLaunchKernelGGL((tile_kernel<L, CGH_BF16, MODE>), dim3(grid), dim3(kTileThreads), 0, s, a);
@@ -813,7 +1034,43 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.in = nullptr;
     a.out = out;
     a.ld = ld;
+    a.dense = lut ? lut->dense_values : nullptr;
+    a.dense_rows = lut ? lut->dense_rows : nullptr;
+    a.n_depth = lut ? lut->prm.n_depth : 0;
+    a.plane_done = nullptr;
+    a.pace_slack = 5;
     return a;
+}
+
+// Workgroups of the dense kernel that fit the device at once (0 if unknown).
+template <int L, int VT, int MODE>
+int64_t capacity_of()
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dense_tile_kernel<L, VT, MODE>, kDenseThreads, 0) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return (int64_t)per_cu * cus;
+}
+
+int64_t resident_capacity(int L, int vt, int mode)
+{
+    static int64_t cache[7][3][2] = {};
+    static bool known[7][3][2] = {};
+    if (known[L][vt][mode]) return cache[L][vt][mode];
+    int64_t c = 0;
+#define CGH_CAP(LL)                                                                                   \
+    if (L == LL) {                                                                                    \
+        if (vt == CGH_F32) c = mode ? capacity_of<LL, CGH_F32, 1>() : capacity_of<LL, CGH_F32, 0>();    \
+        else if (vt == CGH_F16) c = mode ? capacity_of<LL, CGH_F16, 1>() : capacity_of<LL, CGH_F16, 0>(); \
+        else c = mode ? capacity_of<LL, CGH_BF16, 1>() : capacity_of<LL, CGH_BF16, 0>();                \
+    }
+    CGH_CAP(3) CGH_CAP(4) CGH_CAP(5) CGH_CAP(6)
+#undef CGH_CAP
+    (void)hipGetLastError();
+    cache[L][vt][mode] = c;
+    known[L][vt][mode] = true;
+    return c;
 }
 
 int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox,
@@ -827,9 +1084,24 @@ int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, in
     int64_t *tile_off;
     int32_t *tile_pts;
     const wasabi_point *sorted;
-    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts);
+    bool ordered = false;
+    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts, &ordered);
     if (rc) return rc;
-    const TileArgs a = make_args(lut, sorted, tile_off, tile_pts, g, (float2 *)out, ld);
+    TileArgs a = make_args(lut, sorted, tile_off, tile_pts, g, (float2 *)out, ld);
+    // Plane pacing (bounded waits; see the dense kernel) when the lists are in plane order and
+    // every tile of the grid is resident at once.  CGH_PACE=0 switches it off, CGH_PACE_SLACK sets
+    // how many planes a tile may run ahead of the slowest one.
+    static const int pace_env = getenv("CGH_PACE") ? atoi(getenv("CGH_PACE")) : 1;
+    static const int slack_env = getenv("CGH_PACE_SLACK") ? atoi(getenv("CGH_PACE_SLACK")) : 5;
+    if (pace_env && lut->dense && ordered && lut->L >= 3 && lut->prm.n_depth <= kPaceMaxPlanes &&
+        resident_capacity(lut->L, lut->prm.value_dtype, mode) >= (int64_t)g.ntx * g.nty) {
+        int *done;
+        const size_t bytes = sizeof(int) * (size_t)lut->prm.n_depth * kPaceCounters;
+        if ((rc = sc.alloc((void **)&done, bytes))) return rc;
+        CGH_TRY_HIP(hipMemsetAsync(done, 0, bytes, s));
+        a.plane_done = done;
+        a.pace_slack = std::max(1, slack_env);
+    }
     if (mode == MODE_PSI) return launch_tile<MODE_PSI>(lut->L, lut->prm.value_dtype, a, s);
     return launch_tile<MODE_FUSED>(lut->L, lut->prm.value_dtype, a, s);
 }

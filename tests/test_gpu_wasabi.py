@@ -54,8 +54,10 @@ def test_quantize_matches_oracle(orc):
     assert (o.d == -1).sum() > 100 and (o.d >= 0).sum() > 100
 
 
+# gamma < 0.35 runs the sparse (value, key) path, gamma >= 0.35 the dense-block path
 CASES = [(1, 0.3, 0), (2, 0.2, 0), (3, 0.05, 0), (3, 0.6, 0), (4, 0.3, 0), (5, 0.3, 0),
-         (6, 0.5, 0), (3, 0.3, 1), (3, 0.3, 2)]
+         (6, 0.5, 0), (3, 0.3, 1), (3, 0.3, 2), (1, 0.6, 0), (2, 0.5, 0), (4, 0.9, 0),
+         (3, 0.84, 1), (3, 0.84, 2), (5, 1.0, 0)]
 
 
 @pytest.mark.parametrize("levels,gamma,dtype", CASES)
@@ -85,9 +87,10 @@ def test_idwt_matches_oracle(orc, levels):
     assert np.all(got[:, nx:] == 3.0)
 
 
-@pytest.mark.parametrize("levels,sub", [(3, 64), (3, 0), (4, 96), (2, 40)])
-def test_hologram_and_fused_match_oracle(orc, levels, sub):
-    ref, gpu = _luts(orc, levels, 0.25)
+@pytest.mark.parametrize("levels,sub,gamma", [(3, 64, 0.25), (3, 0, 0.25), (4, 96, 0.25),
+                                              (2, 40, 0.25), (3, 64, 0.84), (4, 96, 0.6)])
+def test_hologram_and_fused_match_oracle(orc, levels, sub, gamma):
+    ref, gpu = _luts(orc, levels, gamma)
     B = 1 << levels
     nx, ny, X0, Y0 = (208 // B) * B, (144 // B) * B, -B * 5, -B * 2
     pts = _points(30 + levels, 80, nx + 160, ny + 160, B, x0=X0 - 80, y0=Y0 - 80)
