@@ -63,6 +63,9 @@ const char *cgh_last_error(void);
  *   out_dev : device, ny rows of nx complex values, row stride ld_out elements (ld_out >= nx);
  *             overwritten.  CGH_C64: phase from FP64 r / lambda, FP32 sine/cosine, FP32 sums.
  *             CGH_C128: FP64 throughout.
+ *   With CGH_CIRC and n x (tiles of 64 x 16 pixels) > 2e9 the points are binned by tile first,
+ *   which synchronises `stream` once (to size the per-tile point lists); otherwise the call is
+ *   fully asynchronous.
  * Errors: CGH_EINVAL (n < 0, nx/ny < 1, ld_out < nx, pitch/wavelength not > 0,
  *         wavelength >= 2 pitch, bad enum, NULL pointer with n > 0), CGH_EHIP.  n = 0 writes zeros.
  * ------------------------------------------------------------------------------------------- */

@@ -49,6 +49,9 @@ class Scratch {
 // Keeps the default pool's memory cached between calls (release threshold = unlimited).
 int prepare_pool();
 
+// Exclusive scan of `count` int32 values into int64 offsets (count + 1 values) on stream s.
+int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc, hipStream_t s);
+
 // Records a HIP event pair around the enclosed launches on `s` while tracing is enabled.
 class ProfScope {
   public:

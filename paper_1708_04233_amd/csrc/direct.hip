@@ -1,17 +1,22 @@
 // Eq.(1): u(x_h, y_h) = sum_j a_j exp(i 2 pi r_hj / lambda), the direct superposition of point
 // sources, as a VALU kernel for gfx950.
 //
-// Work split: a 256-thread workgroup owns a 64 x 16 pixel tile; thread t owns column t % 64 and
-// rows t / 64 + 4k (k = 0..3), so the x-distance is shared by its four pixels.  Points stream
-// through LDS in chunks of 256; with the circ() window each chunk is first culled against the
-// tile (a point whose disk misses the whole tile is dropped before any per-pixel work) and the
-// survivors are compacted in their original order, so sums are deterministic.
+// Work split, FULL window: a 256-thread workgroup owns a 64 x 16 pixel tile; thread t owns column
+// t % 64 and rows t / 64 + 4k (k = 0..3), so the x-distance is shared by its four pixels.  Points
+// stream through LDS in chunks of 256.
+// CIRC window: points are first binned by 64 x 64 tile (the bounding box of their disk), and a
+// workgroup sums only its tile's list (16 pixels per thread), so the cost follows the number of
+// (pixel, point) pairs inside the disks rather than pixels x points.
 //
 // Precision: the phase r / lambda reaches thousands of revolutions, so it is formed in FP64 and
 // reduced to its fractional part before the sine and cosine.  For complex64 output r comes from
 // an FP32 reciprocal square root refined by one FP64 Newton step (relative error ~1e-14), the
 // reduced phase goes to the hardware sine/cosine (argument in revolutions) and sums are FP32.
 // For complex128 output everything is FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
 #include "common.hpp"
 
 namespace cgh {
@@ -147,6 +152,194 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a)
     }
 }
 
+// ---- circ() window at scale: points binned by 64 x 16 tile (tiles their disk reaches), then each
+//      tile sums only its own points with the same thread layout as above. ----
+
+struct BinArgs {
+    const double4 *pts;
+    int64_t n;
+    int32_t nx, ny, ntx, nty;
+    int64_t ox, oy;
+    double pitch, tan_t;
+};
+
+// Tile range of the disk's bounding box (pixels, one pixel of margin); false if it misses the window.
+__device__ inline bool disk_tiles(const double4 &p, const BinArgs &b, double &cx, double &cy, double &R,
+                                  int &ty0, int &ty1, int &tx0, int &tx1)
+{
+    if (!(p.z > 0.0) || !isfinite(p.x) || !isfinite(p.y)) return false;
+    R = p.z * b.tan_t / b.pitch;
+    cx = p.x / b.pitch - (double)b.ox;
+    cy = p.y / b.pitch - (double)b.oy;
+    const double x0 = ceil(cx - R - 1.0), x1 = floor(cx + R + 1.0);
+    const double y0 = ceil(cy - R - 1.0), y1 = floor(cy + R + 1.0);
+    if (x1 < 0 || y1 < 0 || x0 > b.nx - 1 || y0 > b.ny - 1) return false;
+    tx0 = (int)(fmax(x0, 0.0) / kTX);
+    tx1 = (int)(fmin(x1, (double)(b.nx - 1)) / kTX) + 1;
+    ty0 = (int)(fmax(y0, 0.0) / kTY);
+    ty1 = (int)(fmin(y1, (double)(b.ny - 1)) / kTY) + 1;
+    return true;
+}
+
+// Does the disk reach tile (ty, tx)?  Distance from the centre to the tile's rectangle of pixel
+// centres, with a one-pixel margin (the exact per-pixel test runs in the summation kernel).
+__device__ inline bool disk_hits(double cx, double cy, double R, int ty, int tx)
+{
+    const double rx0 = tx * kTX, rx1 = rx0 + kTX - 1, ry0 = ty * kTY, ry1 = ry0 + kTY - 1;
+    const double dx = cx - fmin(fmax(cx, rx0), rx1), dy = cy - fmin(fmax(cy, ry0), ry1);
+    return dx * dx + dy * dy < (R + 1.0) * (R + 1.0);
+}
+
+__global__ void disk_count_kernel(BinArgs b, int32_t *counts)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= b.n) return;
+    double cx, cy, R;
+    int ty0, ty1, tx0, tx1;
+    if (!disk_tiles(b.pts[j], b, cx, cy, R, ty0, ty1, tx0, tx1)) return;
+    for (int ty = ty0; ty < ty1; ++ty)
+        for (int tx = tx0; tx < tx1; ++tx)
+            if (disk_hits(cx, cy, R, ty, tx)) atomicAdd(&counts[(int64_t)ty * b.ntx + tx], 1);
+}
+
+__global__ void disk_fill_kernel(BinArgs b, unsigned long long *cursor, int32_t *list)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= b.n) return;
+    double cx, cy, R;
+    int ty0, ty1, tx0, tx1;
+    if (!disk_tiles(b.pts[j], b, cx, cy, R, ty0, ty1, tx0, tx1)) return;
+    for (int ty = ty0; ty < ty1; ++ty)
+        for (int tx = tx0; tx < tx1; ++tx)
+            if (disk_hits(cx, cy, R, ty, tx)) {
+                const unsigned long long slot = atomicAdd(&cursor[(int64_t)ty * b.ntx + tx], 1ull);
+                list[slot] = (int32_t)j;
+            }
+}
+
+template <bool F64>
+__global__ __launch_bounds__(256) void direct_binned_kernel(DirectArgs a, int32_t ntx,
+                                                            const int64_t *tile_off,
+                                                            const int32_t *list)
+{
+    constexpr int ROWS = kRows;
+    __shared__ double4 sp[256];
+    __shared__ double sr2[256];
+    const int tile = blockIdx.x;
+    const int ty = tile / ntx, tx = tile - ty * ntx;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = tx * kTX + lane;
+    const int row0 = ty * kTY + wave;
+    const double xh = (double)(a.ox + col) * a.pitch;
+    double accd_re[ROWS], accd_im[ROWS];
+    float accf_re[ROWS], accf_im[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; k++) {
+        accd_re[k] = accd_im[k] = 0.0;
+        accf_re[k] = accf_im[k] = 0.0f;
+    }
+    const int64_t p0 = tile_off[tile], p1 = tile_off[tile + 1];
+    for (int64_t base = p0; base < p1; base += 256) {
+        const int cnt = (int)min((int64_t)256, p1 - base);
+        if (tid < cnt) {
+            const double4 p = a.pts[list[base + tid]];
+            sp[tid] = make_double4(p.x, p.y, p.z * p.z, p.w);
+            sr2[tid] = p.z * p.z * a.tan2;
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; k++) {
+            const double4 q = sp[k];
+            const double r2lim = sr2[k];
+            const double dx = xh - q.x;
+            const double dx2 = dx * dx;
+#pragma unroll
+            for (int rr = 0; rr < ROWS; rr++) {
+                const double yh = (double)(a.oy + row0 + 4 * rr) * a.pitch;
+                const double dy = yh - q.y;
+                const double rho2 = fma(dy, dy, dx2);
+                const double d2 = rho2 + q.z;
+                if (F64) {
+                    const double amp = (rho2 < r2lim) ? q.w : 0.0;
+                    const double t = sqrt(d2) * a.inv_lambda;
+                    double s, c;
+                    sincospi(2.0 * (t - floor(t)), &s, &c);
+                    accd_re[rr] = fma(amp, c, accd_re[rr]);
+                    accd_im[rr] = fma(amp, s, accd_im[rr]);
+                } else {
+                    const float amp = (rho2 < r2lim) ? (float)q.w : 0.0f;
+                    const float y = __builtin_amdgcn_rsqf((float)d2);
+                    const double r0 = d2 * (double)y;
+                    const double res = fma(-r0, r0, d2);
+                    const double r = fma(res, 0.5 * (double)y, r0);
+                    const double t = r * a.inv_lambda;
+                    const float f = (float)(t - floor(t));
+                    accf_re[rr] = fmaf(amp, __builtin_amdgcn_cosf(f), accf_re[rr]);
+                    accf_im[rr] = fmaf(amp, __builtin_amdgcn_sinf(f), accf_im[rr]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (col < a.nx) {
+#pragma unroll
+        for (int rr = 0; rr < ROWS; rr++) {
+            const int row = row0 + 4 * rr;
+            if (row >= a.ny) continue;
+            if (F64) ((double2 *)a.out)[(int64_t)row * a.ld + col] = make_double2(accd_re[rr], accd_im[rr]);
+            else ((float2 *)a.out)[(int64_t)row * a.ld + col] = make_float2(accf_re[rr], accf_im[rr]);
+        }
+    }
+}
+
+int direct_binned(const DirectArgs &a, double tan_t, bool f64, hipStream_t s)
+{
+    int rc = prepare_pool();
+    if (rc) return rc;
+    BinArgs b;
+    b.pts = a.pts;
+    b.n = a.n;
+    b.nx = a.nx;
+    b.ny = a.ny;
+    b.ntx = (a.nx + kTX - 1) / kTX;
+    b.nty = (a.ny + kTY - 1) / kTY;
+    b.ox = a.ox;
+    b.oy = a.oy;
+    b.pitch = a.pitch;
+    b.tan_t = tan_t;
+    const int64_t ntiles = (int64_t)b.ntx * b.nty;
+    if (ntiles > INT32_MAX) return fail(CGH_EINVAL, "too many tiles");
+    Scratch sc(s);
+    int32_t *counts, *list;
+    int64_t *off;
+    unsigned long long *cursor;
+    if ((rc = sc.alloc((void **)&counts, sizeof(int32_t) * ntiles))) return rc;
+    if ((rc = sc.alloc((void **)&off, sizeof(int64_t) * (ntiles + 1)))) return rc;
+    if ((rc = sc.alloc((void **)&cursor, sizeof(unsigned long long) * ntiles))) return rc;
+    CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
+    const unsigned pblocks = (unsigned)((a.n + 255) / 256);
+    if (a.n > 0) {
+        hipLaunchKernelGGL(disk_count_kernel, dim3(pblocks), dim3(256), 0, s, b, counts);
+        CGH_CHECK_LAUNCH("disk_count_kernel");
+    }
+    if ((rc = scan_counts(counts, ntiles, off, sc, s))) return rc;
+    // the list length depends on the points' depths, which only the device holds: read the total
+    // back (one 8-byte copy, one synchronisation) and size the list exactly
+    int64_t total = 0;
+    CGH_TRY_HIP(hipMemcpyAsync(&total, off + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CGH_TRY_HIP(hipStreamSynchronize(s));
+    if ((rc = sc.alloc((void **)&list, sizeof(int32_t) * std::max<int64_t>(total, 1)))) return rc;
+    if (a.n > 0) {
+        CGH_TRY_HIP(hipMemcpyAsync(cursor, off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(disk_fill_kernel, dim3(pblocks), dim3(256), 0, s, b, cursor, list);
+        CGH_CHECK_LAUNCH("disk_fill_kernel");
+    }
+    ProfScope prof("direct", s);
+    if (f64) hipLaunchKernelGGL(direct_binned_kernel<true>, dim3((unsigned)ntiles), dim3(256), 0, s, a, b.ntx, off, list);
+    else hipLaunchKernelGGL(direct_binned_kernel<false>, dim3((unsigned)ntiles), dim3(256), 0, s, a, b.ntx, off, list);
+    CGH_CHECK_LAUNCH("direct_binned_kernel");
+    return CGH_OK;
+}
+
 }  // namespace
 }  // namespace cgh
 
@@ -177,9 +370,14 @@ extern "C" int cgh_direct(const double *pts, int64_t n, int32_t nx, int32_t ny, 
     a.tan2 = sin_t * sin_t / (1.0 - sin_t * sin_t);
     a.out = out;
     a.ld = ld_out;
-    dim3 grid((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY);
-    if (grid.y > 65535) return fail(CGH_EINVAL, "ny too large");
     const bool f64 = out_dtype == CGH_C128, circ = window == CGH_CIRC;
+    dim3 grid((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY);
+    // circ(): cull every point against every tile while that is cheap, else bin first
+    // (CGH_DIRECT_BIN=1 / 0 forces / forbids binning, for tests and measurements)
+    const char *force = getenv("CGH_DIRECT_BIN");
+    const bool bin = force ? atoi(force) != 0 : (double)n * grid.x * grid.y > 2e9;
+    if (circ && bin) return direct_binned(a, sin_t / std::sqrt(1.0 - sin_t * sin_t), f64, s);
+    if (grid.y > 65535) return fail(CGH_EINVAL, "ny too large");
     ProfScope prof("direct", s);
     if (circ && f64) hipLaunchKernelGGL((direct_kernel<true, true>), grid, dim3(kThreads), 0, s, a);
     else if (circ) hipLaunchKernelGGL((direct_kernel<true, false>), grid, dim3(kThreads), 0, s, a);

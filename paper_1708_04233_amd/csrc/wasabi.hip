@@ -869,6 +869,8 @@ int check_window(int L, int64_t ox, int64_t oy, int32_t nx, int32_t ny)
     return CGH_OK;
 }
 
+}  // namespace
+
 // Exclusive scan of `count` int32 values into int64 offsets (count + 1 values) on stream s.
 int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc, hipStream_t s)
 {
@@ -884,6 +886,8 @@ int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc,
     CGH_CHECK_LAUNCH("scan_add_kernel");
     return CGH_OK;
 }
+
+namespace {
 
 // Plane-sort the points and build the per-tile point lists; results live in `sc`.
 int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,

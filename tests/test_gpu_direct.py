@@ -53,6 +53,25 @@ def test_ragged_window_offset_and_row_stride(orc, dtype):
         assert np.all(got[:, nx:] == 7.0)   # padding columns untouched
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_circ_binned_path(orc, monkeypatch, dtype):
+    """The tile-binned circ() path (used automatically for large problems) on a ragged window."""
+    monkeypatch.setenv("CGH_DIRECT_BIN", "1")
+    pts = uniform_points(9, 400, 200, 120, 20e-6, 150e-6)
+    pts[:, 0] -= 40e-6
+    pts[7, 2] = -1e-6                      # z <= 0 reaches nothing
+    nx, ny, ox, oy = 150, 70, -17, 9
+    ref = orc.direct(pts, nx, ny, ox, oy, window=orc.CIRC)
+    out = torch.full((ny, 160), 2.0, dtype=dtype, device="cuda")
+    cgh.cgh_direct(torch.from_numpy(pts).cuda(), nx, ny, ox, oy, window=cgh.CIRC, out=out)
+    got = out.cpu().numpy()
+    assert _rel(got[:, :nx].astype(np.complex128), ref) < (1e-10 if dtype == torch.complex128 else 1e-5)
+    assert np.all(got[:, nx:] == 2.0)
+    monkeypatch.setenv("CGH_DIRECT_BIN", "1")
+    empty = cgh.cgh_direct(torch.zeros((0, 4), dtype=torch.float64, device="cuda"), 64, 32, window=cgh.CIRC)
+    assert torch.count_nonzero(empty).item() == 0
+
+
 def test_no_points_gives_zeros():
     pts = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
     u = cgh.cgh_direct(pts, 70, 20, window=cgh.CIRC)
