@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-from workloads import WASABI_2048, WASABI_16384, WASABI_65536, grid_points, height_field_points  # noqa: E402
+from workloads import (DIRECT_512, WASABI_2048, WASABI_16384, WASABI_65536, grid_points,  # noqa: E402
+                       height_field_points, poisson_arrivals, serve_points, serve_specs, uniform_points)
 
 METRIC = "hologram Mpixel·points/s WASABI vs direct @PSNR≥40dB; p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
@@ -142,8 +143,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lut", choices=["f32", "f16", "bf16"], default="f32",
                     help="LUT value storage (the 2048^2 workload is specified in FP32)")
-    ap.add_argument("--workload", choices=["2048", "16384", "65536"], default="2048",
-                    help="2048: the headline line; 16384 / 65536: the large holograms")
+    ap.add_argument("--workload", choices=["2048", "16384", "65536", "serve"], default="2048",
+                    help="2048: the headline line; 16384 / 65536: the large holograms; serve: the "
+                         "hologram server under Poisson load")
+    ap.add_argument("--serve-jobs", type=int, default=None,
+                    help="jobs per serving run (default 200 beside the headline line, 1000 for --workload serve)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -166,6 +170,10 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 3 copies of %d bytes" % (a.numel() * 8))
         return
+    if args.workload == "serve":
+        return run_serve_workload(args, torch, cgh)
+    if args.workload == "16384":
+        return run_precision(args, torch, cgh)
     if args.workload != "2048":
         return run_large(args, torch, cgh)
     w = WASABI_2048
@@ -282,6 +290,10 @@ def main():
                "gpu_rel_l2_vs_oracle": float(np.linalg.norm(u40 - uo) / np.linalg.norm(uo))}
         log("cpu oracle %.1fs" % t_cpu)
 
+    serving = serve_run(torch, cgh, serve_lut(cgh), args.serve_jobs or 200, 10, rho=0.8,
+                        budget=64 << 30, slots=4)
+    d512 = direct_512(torch, cgh, args.steps)
+
     value = mpp / (ms_step * 1e-3)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel·points/s", "n_gpus": 1,
@@ -305,6 +317,8 @@ def main():
                              "kernels_ms": {k: round(v, 4) for k, v in split_k.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
+        "direct_512": d512,
     }
     print(json.dumps(out), flush=True)
 
@@ -418,6 +432,195 @@ def run_large(args, torch, cgh):
            "direct": {"ms": round(ms_direct, 2), "value": round(mpp / (ms_direct * 1e-3), 1), "window": "circ"},
            "speedup_vs_direct_at_40db_gamma": round(ms_direct / main["ms_per_step"], 3),
            "paper_context": "paper: ~354 s for a 65536^2 hologram of 95,949 points on one CPU"}
+    print(json.dumps(out), flush=True)
+
+
+def run_precision(args, torch, cgh):
+    """16384^2, N = 2 * 10^5, 64 planes, L = 3, gamma = 0.05 with the LUT values stored as FP32,
+    FP16 and BF16 (FP32 accumulation, FP64 PSF phase in the table).  Per storage type: time per
+    hologram, and on 8 seeded 2^L-aligned 1024^2 windows the PSNR / relative L2 error against the
+    FP64 circ() direct sum of the same snapped points, and the relative difference to the FP32 LUT
+    result (the error the storage type adds)."""
+    w = WASABI_16384
+    nx = ny = w["nx"]
+    n, L = w["n"], w["levels"]
+    B = 1 << L
+    pts_np = grid_points(w["seed"], n, nx, ny, B, w["z_lo"], w["z_hi"])
+    pts = torch.from_numpy(pts_np).cuda()
+    mpp = nx * ny * n / 1e6
+    u = torch.empty((ny, nx), dtype=torch.complex64, device="cuda")
+    rng = np.random.default_rng(8)
+    S = 1024
+    wins = [(int(v[0]) * B, int(v[1]) * B) for v in rng.integers(0, (nx - S) // B, (8, 2))]
+    per, got = {}, {}
+    ref = None
+    for name, vt in (("f32", cgh.F32), ("f16", cgh.F16), ("bf16", cgh.BF16)):
+        prm = cgh.LutParams(n_depth=w["n_depth"], levels=L, gamma=w["gamma"], max_window=w["max_window"],
+                            value_dtype=vt)
+        lut = cgh.wasabi_build_lut(prm)
+        q = cgh.wasabi_quantize(lut, pts)
+
+        def step():
+            cgh.wasabi_quantize(lut, pts, out=q)
+            cgh.wasabi_hologram_fused(lut, q, 0, 0, nx, ny, u=u)
+        steps = max(3, min(args.steps, 10))
+        ms = timed(step, steps, 1, torch)
+        cgh.cgh_profile_reset()
+        cgh.cgh_profile_enable(True)
+        step()
+        torch.cuda.synchronize()
+        cgh.cgh_profile_enable(False)
+        kern = {nm: round(cgh.cgh_profile_query(nm)[0], 3) for nm in ("quantize", "bin", "tile_fused")}
+        cgh.cgh_profile_reset()
+        got[name] = [u[y0:y0 + S, x0:x0 + S].cpu().numpy().astype(np.complex128) for x0, y0 in wins]
+        info = lut.info()
+        per[name] = {"ms_per_step": round(ms, 3), "value": round(mpp / (ms * 1e-3), 1), "kernels_ms": kern,
+                     "lut_entries": int(info["total_entries"]), "lut_device_bytes": int(info["device_bytes"])}
+        if ref is None:
+            qs = q.cpu().numpy()
+            ok = qs[:, 2] >= 0
+            snapped = np.stack([qs[ok, 0] * 1e-6, qs[ok, 1] * 1e-6, info["z"][qs[ok, 2]], pts_np[ok, 3]], axis=1)
+            st = torch.from_numpy(np.ascontiguousarray(snapped)).cuda()
+            ref = [cgh.cgh_direct(st, S, S, x0, y0, window=cgh.CIRC, out_dtype=torch.complex128).cpu().numpy()
+                   for x0, y0 in wins]
+        del lut
+        log("16384", name, per[name])
+    for name in per:
+        num = sum(float(np.sum(np.abs(g - r) ** 2)) for g, r in zip(got[name], ref))
+        den = sum(float(np.sum(np.abs(r) ** 2)) for r in ref)
+        peak = max(float(np.max(np.abs(r)) ** 2) for r in ref)
+        cnt = sum(r.size for r in ref)
+        d32 = sum(float(np.sum(np.abs(g - r) ** 2)) for g, r in zip(got[name], got["f32"]))
+        per[name]["psnr_db_vs_direct"] = round(10 * np.log10(peak / (num / cnt)), 2)
+        per[name]["rel_l2_vs_direct"] = float(np.sqrt(num / den))
+        per[name]["rel_l2_vs_f32_lut"] = float(np.sqrt(d32 / den))
+    main = per["f16"]
+    out = {"metric": METRIC, "value": main["value"], "unit": "Mpixel·points/s", "n_gpus": 1,
+           "steps": max(3, min(args.steps, 10)), "warmup": 1, "ms_per_step": main["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": w["name"], "global_batch": n, "hologram": [ny, nx], "planes": w["n_depth"],
+                      "levels": L, "gamma": w["gamma"], "lut_values": "f16 (also f32, bf16 below)",
+                      "windows": "8 x 1024^2, seed 8"},
+           "per_dtype": per}
+    print(json.dumps(out), flush=True)
+
+
+def circ_interactions(pts, nx, ny, pitch=1e-6, wavelength=633e-9):
+    """(pixel, point) pairs inside the circ() window: pixels strictly within z tan(theta) of the point."""
+    tan_t = (wavelength / (2 * pitch)) / np.sqrt(1 - (wavelength / (2 * pitch)) ** 2)
+    total = 0
+    ys, xs = np.arange(ny), np.arange(nx)
+    for x, y, z, _ in pts:
+        r = z * tan_t / pitch
+        dy2 = (ys - y / pitch) ** 2
+        dx2 = (xs - x / pitch) ** 2
+        total += int(np.count_nonzero(dy2[:, None] + dx2[None, :] < r * r))
+    return total
+
+
+def direct_512(torch, cgh, steps):
+    """The 512^2, N = 10^3 direct sum (Eq.(1)), FULL and circ() windows, complex128 and complex64
+    output: time per hologram and interactions per second."""
+    w = DIRECT_512
+    pts_np = uniform_points(w["seed"], w["n"], w["nx"], w["ny"], w["z_lo"], w["z_hi"])
+    pts = torch.from_numpy(pts_np).cuda()
+    full = w["nx"] * w["ny"] * w["n"]
+    circ = circ_interactions(pts_np, w["nx"], w["ny"])
+    res = {"workload": w["name"], "interactions_full": full, "interactions_circ": circ}
+    for wname, win, cnt in (("full", cgh.FULL, full), ("circ", cgh.CIRC, circ)):
+        for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+            out = torch.empty((w["ny"], w["nx"]), dtype=dt, device="cuda")
+            ms = timed(lambda: cgh.cgh_direct(pts, w["nx"], w["ny"], window=win, out=out), max(steps, 5), 2, torch)
+            res["%s_%s" % (wname, dname)] = {"ms": round(ms, 4), "interactions_per_s": round(cnt / (ms * 1e-3), 1)}
+    return res
+
+
+def serve_lut(cgh):
+    """The serving workload's shared LUT: 64 planes over [0.1, 1.5] mm, L = 3, gamma = 0.05, FP16."""
+    return cgh.wasabi_build_lut(cgh.LutParams(n_depth=64, levels=3, gamma=0.05, max_window=1024,
+                                              value_dtype=cgh.F16))
+
+
+def serve_run(torch, cgh, lut, n_jobs, n_warm, rho, budget, slots, seed=0, solo=None):
+    """One serving run: jobs of the serving mix arrive as a Poisson stream at rho x the solo capacity
+    (jobs/s when run one at a time) and are served by a cgh_server with `slots` streams and a
+    `budget`-byte memory budget.  Latency = done - submit on the server's clock."""
+    import threading
+    specs = serve_specs(seed, n_jobs + n_warm)
+    pts = [serve_points(sp) for sp in specs]
+    with cgh.Server(lut, budget, max_slots=slots) as srv:
+        if solo is None:
+            # solo capacity: the warm-up jobs, then up to 60 more, one at a time
+            k = min(len(specs), n_warm + 60)
+            for i in range(n_warm):
+                t = srv.submit(pts[i], specs[i][0], specs[i][0])
+                srv.wait(t)
+                srv.release(t)
+            t0 = time.perf_counter()
+            for i in range(n_warm, k):
+                t = srv.submit(pts[i], specs[i][0], specs[i][0])
+                srv.wait(t)
+                srv.release(t)
+            solo = (k - n_warm) / (time.perf_counter() - t0)
+        rate = rho * solo
+        arr = poisson_arrivals(seed + 1, n_jobs, rate)
+        tickets = [None] * n_jobs
+        ready = threading.Semaphore(0)
+        lat, gpu = [], []
+
+        def collect():
+            for i in range(n_jobs):
+                ready.acquire()
+                r = srv.wait(tickets[i])
+                lat.append(r["t_done"] - r["t_submit"])
+                gpu.append(r["gpu_ms"])
+                srv.release(tickets[i])
+
+        th = threading.Thread(target=collect)
+        th.start()
+        base = time.perf_counter()
+        for i in range(n_jobs):
+            j = n_warm + i
+            delay = arr[i] - (time.perf_counter() - base)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = srv.submit(pts[j], specs[j][0], specs[j][0])
+            ready.release()
+        th.join()
+        wall = time.perf_counter() - base
+        st = srv.stats()
+    work = sum(specs[n_warm + i][0] ** 2 * specs[n_warm + i][1] for i in range(n_jobs)) / 1e6
+    lat_ms = np.array(lat) * 1e3
+    return {"rho": rho, "budget_bytes": budget, "slots": slots, "jobs": n_jobs,
+            "solo_jobs_per_s": round(solo, 1), "offered_jobs_per_s": round(rate, 1),
+            "jobs_per_s": round(n_jobs / wall, 1), "value": round(work / wall, 1),
+            "unit": "Mpixel·points/s", "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+            "mean_gpu_ms": round(float(np.mean(gpu)), 3), "max_running": st["max_running"],
+            "peak_bytes": st["peak_bytes"], "lut": "f16, 64 planes, L=3, gamma=0.05"}
+
+
+def run_serve_workload(args, torch, cgh):
+    """The serving workload: loads 0.5 / 0.8 / 0.95 of the solo capacity, 64 GB and 4 GB budgets."""
+    lut = serve_lut(cgh)
+    n = args.serve_jobs or 1000
+    runs = []
+    solo = None
+    for budget in (64 << 30, 4 << 30):
+        for rho in (0.5, 0.8, 0.95):
+            r = serve_run(torch, cgh, lut, n, 50, rho, budget, 4, solo=solo)
+            solo = r["solo_jobs_per_s"]
+            runs.append(r)
+            log("serve", r)
+    main = [r for r in runs if r["rho"] == 0.8 and r["budget_bytes"] == 64 << 30][0]
+    out = {"metric": METRIC, "value": main["value"], "unit": "Mpixel·points/s", "n_gpus": 1,
+           "steps": n, "warmup": 50, "ms_per_step": round(1e3 / main["jobs_per_s"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "serve: Poisson jobs, side U{1024,2048,4096,8192}, N lognormal(20000, 1.0) "
+                                  "clipped [1e3, 2e5], FP16 LUT", "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"]},
+           "runs": runs}
     print(json.dumps(out), flush=True)
 
 

@@ -180,6 +180,89 @@ int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, in
                           int64_t ld_u, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Hologram server: a queue of hologram jobs served with continuous batching.
+ *
+ * Every job is one hologram (Sec. 2): its points are snapped (wasabi_quantize) and superposed and
+ * inverted tile by tile (wasabi_hologram_fused) with the server's shared LUT into a
+ * ny x nx complex64 hologram owned by the server.  Up to max_slots jobs run at once, each on a
+ * stream of its own, so the work of different jobs overlaps on the device; a job is admitted
+ * (strictly in submission order) as soon as a slot is free and its memory fits the budget, also
+ * while others run.  The budget counts, per job, its result (8 nx ny bytes, held until
+ * cgh_server_release) and its working memory (device points and the superposition's scratch,
+ * returned when the job ends).  The LUT is not counted.
+ * A scheduler thread owned by the server issues the work; the calls below are thread-safe.
+ * Times are seconds on a monotonic host clock since the server was created.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct cgh_server cgh_server; /* opaque */
+
+typedef struct {
+    size_t hbm_budget_bytes;   /* device memory the jobs may hold together (> 0)                  */
+    int32_t max_slots;         /* jobs running at once, 1 .. 64                                   */
+    int32_t simulate;          /* 0: run on the device of `lut`.  1: host model, no device work:
+                                  a job "runs" for sim_ns_per_pixel * nx * ny ns (for testing the
+                                  admission policy without a GPU; results have u = NULL)          */
+    double sim_ns_per_pixel;
+    const wasabi_lut *lut;     /* shared by every job; must outlive the server (ignored when
+                                  simulate = 1 and NULL is given: jobs then need multiples of 8)  */
+} cgh_server_config;
+
+typedef struct {
+    const double *host_pts; /* host, n x 4 double {x, y, z, a} metres as for wasabi_quantize;
+                               copied by cgh_server_submit (the caller may reuse it at once)      */
+    int64_t n;              /* 0 .. 2^31 - 1                                                      */
+    int32_t nx, ny;         /* hologram size, positive multiples of 2^L, at most 65536 each       */
+} cgh_job;
+
+typedef struct {
+    const void *u;          /* device, ny x nx complex64 row-major, valid until release; NULL for
+                               a cancelled or failed job and in simulation                        */
+    int32_t nx, ny;
+    double t_submit, t_admit, t_start, t_done; /* submit call, admission, work issued, work done  */
+    double gpu_ms;          /* device time of the job's work (HIP events on its stream)           */
+    int32_t status;         /* CGH_OK, CGH_ECANCELED, or the error code of the failed job         */
+    int32_t slot;           /* slot (stream) that ran it, -1 if it never ran                      */
+} cgh_result;
+
+typedef struct {
+    int64_t submitted, completed, canceled, failed; /* jobs by final state (completed = OK)       */
+    int64_t queued, running;                        /* now                                        */
+    int64_t max_running;                            /* most jobs running at once so far           */
+    size_t bytes_in_use, peak_bytes;                /* budgeted bytes now / at most so far        */
+} cgh_server_stats;
+
+/* Create a server on the current device (the LUT's).  Errors: CGH_EINVAL (NULL arguments, budget 0,
+ * max_slots out of range, LUT on another device), CGH_EHIP. */
+int cgh_server_create(const cgh_server_config *cfg, cgh_server **out);
+
+/* Queue a job; *ticket identifies it (> 0).  Errors: CGH_EINVAL (bad sizes, NULL points with
+ * n > 0), CGH_ENOMEM (the job alone exceeds the budget, or host staging memory failed),
+ * CGH_ECANCELED (the server is shutting down), CGH_EHIP. */
+int cgh_server_submit(cgh_server *srv, const cgh_job *job, uint64_t *ticket);
+
+/* Wait until the job has ended (done, failed or cancelled) and describe it in *out.  timeout_ms < 0
+ * waits without limit.  Returns CGH_OK when the job has ended (its own outcome is out->status),
+ * CGH_ETIMEDOUT, CGH_ENOTFOUND (unknown or released ticket), CGH_ECANCELED (server destroyed
+ * while waiting). */
+int cgh_server_wait(cgh_server *srv, uint64_t ticket, int32_t timeout_ms, cgh_result *out);
+
+/* Cancel a queued or running job: a queued job ends at once, a running one when its device work
+ * ends (that work is not interrupted); either way it ends with status CGH_ECANCELED and holds no
+ * memory.  Errors: CGH_ENOTFOUND, CGH_EINVAL (the job has already ended: release it instead). */
+int cgh_server_cancel(cgh_server *srv, uint64_t ticket);
+
+/* Forget an ended job and give its result memory back to the budget.  The caller must have
+ * finished (synchronised) any device work that reads the result.  Errors: CGH_ENOTFOUND,
+ * CGH_EAGAIN (the job has not ended yet). */
+int cgh_server_release(cgh_server *srv, uint64_t ticket);
+
+/* Current counters.  Errors: CGH_EINVAL. */
+int cgh_server_query(cgh_server *srv, cgh_server_stats *out);
+
+/* Cancel the queued jobs, wait for the running ones, wake every waiter (CGH_ECANCELED) and free the
+ * server with all results.  No other call may use `srv` once this returns.  NULL is accepted. */
+int cgh_server_destroy(cgh_server *srv);
+
+/* ---------------------------------------------------------------------------------------------
  * Kernel tracing.  While enabled, the library records a pair of HIP events on the launching
  * stream around each of its kernels (or kernel groups), under these names:
  *   "direct", "quantize", "psf_haar", "select", "bin" (count + scan + fill), "tile_superpose",

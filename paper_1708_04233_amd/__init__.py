@@ -12,6 +12,7 @@ the C ABI in ``include/cgh.h``:
   wasabi_idwt             inverse Haar transform (Sec. 2 step 3)
   wasabi_hologram         sub-hologram procedure (Sec. 2, large-scale steps 2-4)
   wasabi_hologram_fused   the same, tile by tile in on-chip memory
+  Server                  cgh_server_*: hologram jobs with continuous batching under a memory budget
 """
 from __future__ import annotations
 
@@ -48,6 +49,32 @@ class _LutParams(ctypes.Structure):
                 ("gamma", ctypes.c_double)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("simulate", ctypes.c_int32), ("sim_ns_per_pixel", ctypes.c_double),
+                ("lut", ctypes.c_void_p)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("host_pts", ctypes.c_void_p), ("n", ctypes.c_int64), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("gpu_ms", ctypes.c_double), ("status", ctypes.c_int32), ("slot", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("canceled", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("max_running", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t),
+                ("peak_bytes", ctypes.c_size_t)]
+
+
 _lib = None
 
 
@@ -73,6 +100,13 @@ def load() -> ctypes.CDLL:
         "wasabi_idwt": ([P, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram": ([P, P, I64, I64, I64, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram_fused": ([P, P, I64, I64, I64, I32, I32, P, I64, P], ctypes.c_int),
+        "cgh_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(P)], ctypes.c_int),
+        "cgh_server_submit": ([P, ctypes.POINTER(_Job), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "cgh_server_wait": ([P, ctypes.c_uint64, I32, ctypes.POINTER(_Result)], ctypes.c_int),
+        "cgh_server_cancel": ([P, ctypes.c_uint64], ctypes.c_int),
+        "cgh_server_release": ([P, ctypes.c_uint64], ctypes.c_int),
+        "cgh_server_query": ([P, ctypes.POINTER(_Stats)], ctypes.c_int),
+        "cgh_server_destroy": ([P], ctypes.c_int),
         "cgh_profile_enable": ([I32], ctypes.c_int),
         "cgh_profile_reset": ([], ctypes.c_int),
         "cgh_profile_query": ([ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)], ctypes.c_int),
@@ -289,3 +323,78 @@ def wasabi_hologram_fused(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, 
                                         oy, nx, ny, ctypes.c_void_p(u.data_ptr()), u.stride(0),
                                         _stream()))
     return u
+
+
+class _DeviceArray:
+    """A device buffer owned by the library, seen by torch through __cuda_array_interface__."""
+
+    def __init__(self, ptr: int, shape):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": "<f4", "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+class Server:
+    """cgh_server_*: a queue of hologram jobs (host points -> ny x nx complex64 hologram) served with
+    continuous batching on `max_slots` streams under a device-memory budget.  simulate=True models
+    the schedule on the host only (no device work; results carry no hologram)."""
+
+    def __init__(self, lut: Lut | None, hbm_budget_bytes: int, max_slots: int = 4,
+                 simulate: bool = False, sim_ns_per_pixel: float = 0.0):
+        self._lut = lut  # keeps the LUT alive while the server exists
+        cfg = _ServerConfig(hbm_budget_bytes, max_slots, 1 if simulate else 0, sim_ns_per_pixel,
+                            lut.handle if lut is not None else None)
+        h = ctypes.c_void_p()
+        _check(load().cgh_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, pts: np.ndarray | None, nx: int, ny: int) -> int:
+        """Queue one hologram of the (n, 4) float64 host points {x, y, z, a} (metres); returns the ticket."""
+        if pts is None:
+            pts = np.zeros((0, 4))
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 4:
+            raise ValueError("pts must be (n, 4)")
+        job = _Job(pts.ctypes.data if len(pts) else None, len(pts), nx, ny)
+        t = ctypes.c_uint64()
+        _check(load().cgh_server_submit(self.handle, ctypes.byref(job), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> dict:
+        """Wait for a job; returns its times, status and (if done) the hologram as a torch view of the
+        server's buffer, valid until release()."""
+        r = _Result()
+        _check(load().cgh_server_wait(self.handle, ticket, timeout_ms, ctypes.byref(r)))
+        u = None
+        if r.u:
+            u = torch.view_as_complex(torch.as_tensor(_DeviceArray(r.u, (r.ny, r.nx, 2)), device="cuda"))
+        return {"u": u, "nx": r.nx, "ny": r.ny, "t_submit": r.t_submit, "t_admit": r.t_admit,
+                "t_start": r.t_start, "t_done": r.t_done, "gpu_ms": r.gpu_ms, "status": r.status,
+                "slot": r.slot}
+
+    def cancel(self, ticket: int):
+        _check(load().cgh_server_cancel(self.handle, ticket))
+
+    def release(self, ticket: int):
+        _check(load().cgh_server_release(self.handle, ticket))
+
+    def stats(self) -> dict:
+        st = _Stats()
+        _check(load().cgh_server_query(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _Stats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(load().cgh_server_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -46,7 +46,8 @@ class Scratch {
     std::vector<void *> ptrs_;
 };
 
-// Keeps the default pool's memory cached between calls (release threshold = unlimited).
+// Keeps the default pool's memory cached between calls (release threshold = unlimited) and stops it
+// from making one stream wait for another to reuse memory.
 int prepare_pool();
 
 // Exclusive scan of `count` int32 values into int64 offsets (count + 1 values) on stream s.
@@ -136,4 +137,13 @@ namespace cgh {
 // Geometry of the planes (Sec. 2, step 1); fills z, R, W, Nr of `lut`.  Returns CGH_OK or CGH_EINVAL.
 int lut_geometry(wasabi_lut *lut);
 int validate_params(const wasabi_lut_params *prm);
+
+// Upper bound (bytes) of the device scratch wasabi_hologram_fused takes from the stream-ordered
+// pool for n points on an nx x ny window at origin (0, 0).
+int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny);
+
+// wasabi_hologram_fused at origin (0, 0), u contiguous, without plane pacing: for work that shares
+// the device with other streams, where the tiles of one launch cannot count on being co-resident.
+int hologram_fused_shared(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int32_t nx,
+                          int32_t ny, void *u, hipStream_t s);
 }  // namespace cgh

@@ -53,6 +53,10 @@ int prepare_pool()
     CGH_TRY_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
     uint64_t thr = UINT64_MAX;
     CGH_TRY_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    // Memory freed on one stream is reused by another only once its work has finished: the pool
+    // must not make one stream wait for another (work on different streams stays independent).
+    int no = 0;
+    CGH_TRY_HIP(hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &no));
     done.push_back(dev);
     return CGH_OK;
 }

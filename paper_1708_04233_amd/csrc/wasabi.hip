@@ -20,6 +20,7 @@
 // idwt_kernel gathers a tile from a Mallat-layout field, inverts it in LDS and writes pixels.
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -889,21 +890,42 @@ int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc,
 
 namespace {
 
+// Bins of the plane sort: (plane, 64-row band of the point's y) pairs plus one for invalid points.
+int sort_bands(const wasabi_lut *lut, const TileGeom &g)
+{
+    const int nd = lut->prm.n_depth;
+    int nyb = (int)std::min<int64_t>(((int64_t)g.ny + 2 * lut->max_span_px + 63) / 64, 4096);
+    if ((int64_t)nyb * nd + 1 > (INT64_C(1) << 26)) nyb = std::max(1, (1 << 26) / nd - 1);
+    return nyb;
+}
+
+// (tile, point) pairs the lists can hold: every point meets at most per_point tiles.
+int64_t pair_bound(const wasabi_lut *lut, int64_t n, const TileGeom &g)
+{
+    const int64_t ntiles = (int64_t)g.ntx * g.nty;
+    const int64_t per_side = (lut->max_span_px + kT - 1) / kT + 1;
+    const int64_t per_point = std::min<int64_t>(per_side * per_side, ntiles);
+    return std::max<int64_t>(n * per_point, 1);
+}
+
+bool use_matrix_path(int64_t n, int64_t ntiles)
+{
+    const int64_t nwg = (n + kChunk - 1) / kChunk;
+    return n > 0 && ntiles <= kMaxLdsTiles && nwg * ntiles <= (INT64_C(1) << 24);
+}
+
 // Plane-sort the points and build the per-tile point lists; results live in `sc`.
 int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,
                Scratch &sc, hipStream_t s, const wasabi_point **sorted_out,
                int64_t **tile_off_out, int32_t **tile_pts_out, bool *ordered_out)
 {
     const int64_t ntiles = (int64_t)g.ntx * g.nty;
-    const int64_t per_side = (lut->max_span_px + kT - 1) / kT + 1;
-    const int64_t per_point = std::min<int64_t>(per_side * per_side, ntiles);
-    const int64_t bound = std::max<int64_t>(n * per_point, 1);
+    const int64_t bound = pair_bound(lut, n, g);
     const int nd = lut->prm.n_depth, L = lut->L;
     SortKey key;
     key.n_depth = nd;
     key.y0 = g.oy - lut->max_span_px;
-    key.nyb = (int)std::min<int64_t>(((int64_t)g.ny + 2 * lut->max_span_px + 63) / 64, 4096);
-    if ((int64_t)key.nyb * nd + 1 > (INT64_C(1) << 26)) key.nyb = std::max(1, (1 << 26) / nd - 1);
+    key.nyb = sort_bands(lut, g);
     const int nbins = nd * key.nyb + 1;
     int32_t *counts, *dcounts;
     int64_t *off, *doff;
@@ -945,7 +967,7 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     const int64_t nwg = (n + kChunk - 1) / kChunk;
     const unsigned pblocks = (unsigned)((n + 255) / 256);
     *ordered_out = false;
-    if (n > 0 && ntiles <= kMaxLdsTiles && nwg * ntiles <= (INT64_C(1) << 24)) {
+    if (use_matrix_path(n, ntiles)) {
         *ordered_out = true;
         int32_t *mat;
         int64_t *moff;
@@ -1059,8 +1081,10 @@ int64_t capacity_of()
 
 int64_t resident_capacity(int L, int vt, int mode)
 {
+    static std::mutex mu;
     static int64_t cache[7][3][2] = {};
     static bool known[7][3][2] = {};
+    std::lock_guard<std::mutex> lock(mu);
     if (known[L][vt][mode]) return cache[L][vt][mode];
     int64_t c = 0;
 #define CGH_CAP(LL)                                                                                   \
@@ -1079,7 +1103,7 @@ int64_t resident_capacity(int L, int vt, int mode)
 
 int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox,
                    int64_t oy, int32_t nx, int32_t ny, void *out, int64_t ld, int mode,
-                   hipStream_t s)
+                   hipStream_t s, bool allow_pace = true)
 {
     int rc = prepare_pool();
     if (rc) return rc;
@@ -1097,7 +1121,7 @@ int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, in
     // how many planes a tile may run ahead of the slowest one.
     static const int pace_env = getenv("CGH_PACE") ? atoi(getenv("CGH_PACE")) : 1;
     static const int slack_env = getenv("CGH_PACE_SLACK") ? atoi(getenv("CGH_PACE_SLACK")) : 5;
-    if (pace_env && lut->dense && ordered && lut->L >= 3 && lut->prm.n_depth <= kPaceMaxPlanes &&
+    if (allow_pace && pace_env && lut->dense && ordered && lut->L >= 3 && lut->prm.n_depth <= kPaceMaxPlanes &&
         resident_capacity(lut->L, lut->prm.value_dtype, mode) >= (int64_t)g.ntx * g.nty) {
         int *done;
         const size_t bytes = sizeof(int) * (size_t)lut->prm.n_depth * kPaceCounters;
@@ -1146,6 +1170,34 @@ int idwt_impl(const void *psi, int32_t nx, int32_t ny, int32_t levels, void *u, 
 }
 
 }  // namespace
+
+int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny)
+{
+    const TileGeom g = make_geom(0, 0, nx, ny);
+    const int64_t ntiles = (int64_t)g.ntx * g.nty;
+    const int64_t nbins = (int64_t)lut->prm.n_depth * sort_bands(lut, g) + 1;
+    auto r = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
+    auto scan = [&](int64_t count) { return r(8 * ((count + 1023) / 1024)); };
+    int64_t t = r(4 * ntiles) + r(8 * (ntiles + 1)) + r(8 * ntiles) + r(4 * pair_bound(lut, n, g)) +
+                r(4 * nbins) + r(8 * (nbins + 1)) + r(8 * nbins) + r(16 * std::max<int64_t>(n, 1)) +
+                scan(nbins);
+    if (use_matrix_path(n, ntiles)) {
+        const int64_t cells = (n + kChunk - 1) / kChunk * ntiles;
+        t += r(4 * cells) + r(8 * (cells + 1)) + scan(cells);
+    } else {
+        t += scan(ntiles);
+    }
+    return t;
+}
+
+int hologram_fused_shared(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int32_t nx,
+                          int32_t ny, void *u, hipStream_t s)
+{
+    int rc = check_common(lut, pts, n, 0, 0, nx, ny, u);
+    if (rc) return rc;
+    return superpose_impl(lut, pts, n, 0, 0, nx, ny, u, nx, MODE_FUSED, s, false);
+}
+
 }  // namespace cgh
 
 extern "C" int wasabi_superpose(const wasabi_lut *lut, const wasabi_point *pts, int64_t n,

@@ -1,0 +1,142 @@
+"""Full-size parity: the 65536^2 hologram (N = 10^6 on a height field, 256 planes, L = 4,
+gamma = 0.02, FP32 LUT) and the 16384^2 hologram (N = 2 * 10^5, 64 planes, L = 3, gamma = 0.05,
+FP16 and BF16 LUT values) computed whole on the GPU in the launch configuration the benchmark
+times, checked on sampled windows against the FP64 oracle with the same (oracle-built) LUT.
+
+For a window the oracle is given only the points whose PSF table can reach it (table half-side
+<= max_window / 2): the others add nothing to it, so the window is the same."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1708_04233_amd as cgh
+from workloads import WASABI_16384, WASABI_65536, grid_points, height_field_points
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+WIN = 256
+
+
+def near(q, x0, y0, w, reach):
+    keep = ((q.x >= x0 - reach) & (q.x < x0 + w + reach) & (q.y >= y0 - reach) & (q.y < y0 + w + reach))
+    return type(q)(q.x[keep], q.y[keep], q.d[keep], q.a[keep])
+
+
+def windows(seed, side, B, k):
+    rng = np.random.default_rng(seed)
+    out = [(0, 0), (side - WIN, side - WIN)]                    # two corners of the hologram
+    out += [(int(v[0]) * B, int(v[1]) * B) for v in rng.integers(0, (side - WIN) // B, (k, 2))]
+    return out
+
+
+def check_windows(orc, olut, oq, u, side, B, seed, k=3):
+    reach = olut.params.max_window // 2 + B
+    worst = 0.0
+    for x0, y0 in windows(seed, side, B, k):
+        want = orc.wasabi(olut, near(oq, x0, y0, WIN, reach), x0, y0, WIN, WIN)
+        got = u[y0:y0 + WIN, x0:x0 + WIN].cpu().numpy().astype(np.complex128)
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        worst = max(worst, err)
+        assert err <= TOL, (x0, y0, err)
+    return worst
+
+
+@pytest.fixture(scope="module")
+def big(orc):
+    w = WASABI_65536
+    kw = dict(n_depth=w["n_depth"], levels=w["levels"], gamma=w["gamma"], max_window=w["max_window"])
+    olut = orc.build_lut(orc.LutParams(**kw))
+    lut = cgh.wasabi_lut_import(cgh.LutParams(**kw), olut.off, olut.idx, olut.val)
+    B = 1 << w["levels"]
+    pts = height_field_points(w["seed"], w["n"], w["nx"], B, w["z_lo"], w["z_hi"])
+    q = cgh.wasabi_quantize(lut, torch.from_numpy(pts).cuda())
+    u = torch.empty((w["ny"], w["nx"]), dtype=torch.complex64, device="cuda")
+    cgh.wasabi_hologram_fused(lut, q, 0, 0, w["nx"], w["ny"], u=u)
+    torch.cuda.synchronize()
+    yield w, olut, lut, q, u, orc.quantize(pts, olut.params)
+    del u
+    torch.cuda.empty_cache()
+
+
+def test_65536_fused_windows(orc, big):
+    w, olut, lut, q, u, oq = big
+    check_windows(orc, olut, oq, u, w["nx"], 1 << w["levels"], seed=3)
+
+
+def test_65536_subhologram_procedure_windows(orc, big):
+    """The paper's procedure (8192^2 sub-holograms: superpose into a wavelet field, invert) gives
+    the same hologram as the fused path."""
+    w, olut, lut, q, u, oq = big
+    B = 1 << w["levels"]
+    wins = windows(4, w["nx"], B, 3)
+    before = [u[y0:y0 + WIN, x0:x0 + WIN].clone() for x0, y0 in wins]
+    cgh.wasabi_hologram(lut, q, 0, 0, w["nx"], w["ny"], sub=8192, u=u)
+    torch.cuda.synchronize()
+    for (x0, y0), b in zip(wins, before):
+        a = u[y0:y0 + WIN, x0:x0 + WIN]
+        assert float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) <= 1e-6
+    check_windows(orc, olut, oq, u, w["nx"], B, seed=5, k=1)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_16384_reduced_precision_windows(orc, dtype):
+    w = WASABI_16384
+    vt = {"f16": (orc.F16, cgh.F16), "bf16": (orc.BF16, cgh.BF16)}[dtype]
+    kw = dict(n_depth=w["n_depth"], levels=w["levels"], gamma=w["gamma"], max_window=w["max_window"])
+    olut = orc.build_lut(orc.LutParams(value_dtype=vt[0], **kw))
+    lut = cgh.wasabi_lut_import(cgh.LutParams(value_dtype=vt[1], **kw), olut.off, olut.idx, olut.val)
+    B = 1 << w["levels"]
+    pts = grid_points(w["seed"], w["n"], w["nx"], w["ny"], B, w["z_lo"], w["z_hi"])
+    q = cgh.wasabi_quantize(lut, torch.from_numpy(pts).cuda())
+    u = cgh.wasabi_hologram_fused(lut, q, 0, 0, w["nx"], w["ny"])
+    torch.cuda.synchronize()
+    check_windows(orc, olut, orc.quantize(pts, olut.params), u, w["nx"], B, seed=6)
+
+
+# Storage precision (LUT values rounded to nearest even): a rounded value carries a relative error
+# uniform in +-2^-(p+1) (p = 10 fraction bits for FP16, 7 for BF16, 23 for FP32), RMS 2^-p / sqrt(12);
+# the hologram sums such terms with independent errors, so its relative L2 error is about the
+# same.  FP16: 2.8e-4, BF16: 2.3e-3, FP32: 7e-8 (then FP32 accumulation dominates).  The bounds
+# below leave a factor of ~3.
+PREC_BOUND = {"f32": 1e-5, "f16": 1e-3, "bf16": 8e-3}
+
+
+@pytest.fixture(scope="module")
+def fp64_windows(orc):
+    """The 16384^2 workload's hologram on 8 seeded 2^L-aligned 2048^2 windows, by the oracle with
+    the LUT values kept in FP64."""
+    w = WASABI_16384
+    B = 1 << w["levels"]
+    prm = orc.LutParams(n_depth=w["n_depth"], levels=w["levels"], gamma=w["gamma"],
+                        max_window=w["max_window"], value_dtype=orc.F64)
+    olut = orc.build_lut(prm)
+    pts = grid_points(w["seed"], w["n"], w["nx"], w["ny"], B, w["z_lo"], w["z_hi"])
+    oq = orc.quantize(pts, prm)
+    rng = np.random.default_rng(9)
+    S = 2048
+    wins = [(int(v[0]) * B, int(v[1]) * B) for v in rng.integers(0, (w["nx"] - S) // B, (8, 2))]
+    reach = w["max_window"] // 2 + B
+    refs = [orc.wasabi(olut, near(oq, x0, y0, S, reach), x0, y0, S, S) for x0, y0 in wins]
+    return pts, wins, refs, S
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_16384_storage_precision_vs_fp64(fp64_windows, dtype):
+    """The library's own LUT (built on the GPU) at each storage type against FP64 values."""
+    w = WASABI_16384
+    pts, wins, refs, S = fp64_windows
+    vt = {"f32": cgh.F32, "f16": cgh.F16, "bf16": cgh.BF16}[dtype]
+    lut = cgh.wasabi_build_lut(cgh.LutParams(n_depth=w["n_depth"], levels=w["levels"], gamma=w["gamma"],
+                                             max_window=w["max_window"], value_dtype=vt))
+    q = cgh.wasabi_quantize(lut, torch.from_numpy(pts).cuda())
+    u = cgh.wasabi_hologram_fused(lut, q, 0, 0, w["nx"], w["ny"])
+    torch.cuda.synchronize()
+    num = den = 0.0
+    for (x0, y0), ref in zip(wins, refs):
+        got = u[y0:y0 + S, x0:x0 + S].cpu().numpy().astype(np.complex128)
+        num += float(np.sum(np.abs(got - ref) ** 2))
+        den += float(np.sum(np.abs(ref) ** 2))
+    err = float(np.sqrt(num / den))
+    print("16384^2 %s LUT: relative L2 error vs FP64 oracle on 8 x 2048^2 windows = %.3e" % (dtype, err))
+    assert err <= PREC_BOUND[dtype]

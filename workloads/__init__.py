@@ -73,18 +73,23 @@ WASABI_16384 = dict(name="wasabi-16384x16384-n2e5-L3-64planes", nx=16384, ny=163
                     seed=0)
 
 
-def serve_jobs(seed: int, n_jobs: int, sizes=(1024, 2048, 4096, 8192), median_n: float = 20_000,
-               sigma: float = 1.0, n_lo: int = 1000, n_hi: int = 200_000, grid: int = 8,
-               z_lo: float = 0.1e-3, z_hi: float = 1.5e-3):
-    """Job mix of the serving workload: side uniform over `sizes`, N log-normal (clipped),
-    points on the grid inside each job's own hologram.  Returns a list of (side, pts)."""
+def serve_specs(seed: int, n_jobs: int, sizes=(1024, 2048, 4096, 8192), median_n: float = 20_000,
+                sigma: float = 1.0, n_lo: int = 1000, n_hi: int = 200_000):
+    """Job mix of the serving workload: hologram side uniform over `sizes`, N log-normal with the
+    given median and sigma, clipped to [n_lo, n_hi].  Returns (side, n, point_seed) per job."""
     rng = np.random.default_rng(seed)
-    jobs = []
+    out = []
     for i in range(n_jobs):
         side = int(rng.choice(sizes))
         n = int(np.clip(np.exp(rng.normal(np.log(median_n), sigma)), n_lo, n_hi))
-        jobs.append((side, grid_points(seed * 1_000_003 + i + 1, n, side, side, grid, z_lo, z_hi)))
-    return jobs
+        out.append((side, n, seed * 1_000_003 + i + 1))
+    return out
+
+
+def serve_points(spec, grid: int = 8, z_lo: float = 0.1e-3, z_hi: float = 1.5e-3) -> np.ndarray:
+    """Points of one serving job: on the 2^L grid inside the job's own hologram, z uniform."""
+    side, n, pseed = spec
+    return grid_points(pseed, n, side, side, grid, z_lo, z_hi)
 
 
 def poisson_arrivals(seed: int, n_jobs: int, rate_per_s: float) -> np.ndarray:
