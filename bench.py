@@ -291,7 +291,7 @@ def main():
         log("cpu oracle %.1fs" % t_cpu)
 
     serving = serve_run(torch, cgh, serve_lut(cgh), args.serve_jobs or 200, 10, rho=0.8,
-                        budget=64 << 30, slots=4)
+                        budget=64 << 30, slots=3)
     d512 = direct_512(torch, cgh, args.steps)
 
     value = mpp / (ms_step * 1e-3)
@@ -567,7 +567,7 @@ def serve_run(torch, cgh, lut, n_jobs, n_warm, rho, budget, slots, seed=0, solo=
         arr = poisson_arrivals(seed + 1, n_jobs, rate)
         tickets = [None] * n_jobs
         ready = threading.Semaphore(0)
-        lat, gpu = [], []
+        lat, gpu, parts = [], [], []
 
         def collect():
             for i in range(n_jobs):
@@ -575,6 +575,7 @@ def serve_run(torch, cgh, lut, n_jobs, n_warm, rho, budget, slots, seed=0, solo=
                 r = srv.wait(tickets[i])
                 lat.append(r["t_done"] - r["t_submit"])
                 gpu.append(r["gpu_ms"])
+                parts.append((r["t_admit"] - r["t_submit"], r["t_start"] - r["t_admit"], r["t_done"] - r["t_start"]))
                 srv.release(tickets[i])
 
         th = threading.Thread(target=collect)
@@ -598,6 +599,9 @@ def serve_run(torch, cgh, lut, n_jobs, n_warm, rho, budget, slots, seed=0, solo=
             "unit": "Mpixel·points/s", "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
             "mean_gpu_ms": round(float(np.mean(gpu)), 3), "max_running": st["max_running"],
+            "mean_queue_ms": round(float(np.mean([p[0] for p in parts])) * 1e3, 3),
+            "mean_issue_ms": round(float(np.mean([p[1] for p in parts])) * 1e3, 3),
+            "mean_run_ms": round(float(np.mean([p[2] for p in parts])) * 1e3, 3),
             "peak_bytes": st["peak_bytes"], "lut": "f16, 64 planes, L=3, gamma=0.05"}
 
 
@@ -609,7 +613,7 @@ def run_serve_workload(args, torch, cgh):
     solo = None
     for budget in (64 << 30, 4 << 30):
         for rho in (0.5, 0.8, 0.95):
-            r = serve_run(torch, cgh, lut, n, 50, rho, budget, 4, solo=solo)
+            r = serve_run(torch, cgh, lut, n, 50, rho, budget, 3, solo=solo)
             solo = r["solo_jobs_per_s"]
             runs.append(r)
             log("serve", r)

@@ -91,7 +91,8 @@ typedef struct {
     int32_t n_depth;     /* number of planes, 1 .. 65536                                       */
     int32_t levels;      /* wavelet levels L, 1 .. 6                                           */
     int32_t max_window;  /* largest allowed table side; every W_d must fit (else CGH_EINVAL),
-                            and W_d <= 2^(16 - L)                                              */
+                            and W_d / 2^L <= 65536 / (4^L + pad(L)) (the 16-bit entry keys):
+                            W_d up to about 7900 (L = 3) or 4000 (L = 4) pixels               */
     int32_t value_dtype; /* CGH_F32, CGH_F16 or CGH_BF16                                       */
     double gamma;        /* selectivity, > 0                                                   */
 } wasabi_lut_params;
@@ -187,10 +188,15 @@ int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, in
  * ny x nx complex64 hologram owned by the server.  Up to max_slots jobs run at once, each on a
  * stream of its own, so the work of different jobs overlaps on the device; a job is admitted
  * (strictly in submission order) as soon as a slot is free and its memory fits the budget, also
- * while others run.  The budget counts, per job, its result (8 nx ny bytes, held until
- * cgh_server_release) and its working memory (device points and the superposition's scratch,
- * returned when the job ends).  The LUT is not counted.
+ * while others run.  The budget counts the device memory the server holds: each job's result
+ * (8 nx ny bytes, held until cgh_server_release) and each slot's arena, which holds the working
+ * memory of the job running in it (device points, quantised points, the superposition's scratch),
+ * is kept for the slot's next job, grows for a larger one and is given back when an idle slot's
+ * share is needed to admit a job.  The LUT is not counted.
  * A scheduler thread owned by the server issues the work; the calls below are thread-safe.
+ * Each slot is a stream: keep max_slots + the caller's own streams within the device's hardware
+ * queues per process (GPU_MAX_HW_QUEUES, 4 by default), or enqueue calls start to wait on each
+ * other; 2-3 slots overlap one job's host-side issue with the device work of others.
  * Times are seconds on a monotonic host clock since the server was created.
  * ------------------------------------------------------------------------------------------- */
 typedef struct cgh_server cgh_server; /* opaque */
@@ -217,7 +223,8 @@ typedef struct {
     const void *u;          /* device, ny x nx complex64 row-major, valid until release; NULL for
                                a cancelled or failed job and in simulation                        */
     int32_t nx, ny;
-    double t_submit, t_admit, t_start, t_done; /* submit call, admission, work issued, work done  */
+    double t_submit, t_admit, t_start, t_done; /* submit call, admission, all work enqueued on the
+                                                  job's stream, work seen done                    */
     double gpu_ms;          /* device time of the job's work (HIP events on its stream)           */
     int32_t status;         /* CGH_OK, CGH_ECANCELED, or the error code of the failed job         */
     int32_t slot;           /* slot (stream) that ran it, -1 if it never ran                      */
@@ -228,6 +235,7 @@ typedef struct {
     int64_t queued, running;                        /* now                                        */
     int64_t max_running;                            /* most jobs running at once so far           */
     size_t bytes_in_use, peak_bytes;                /* budgeted bytes now / at most so far        */
+    size_t arena_bytes;                             /* of bytes_in_use: the slots' arenas         */
 } cgh_server_stats;
 
 /* Create a server on the current device (the LUT's).  Errors: CGH_EINVAL (NULL arguments, budget 0,

@@ -72,7 +72,7 @@ class _Stats(ctypes.Structure):
                 ("canceled", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
                 ("max_running", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t),
-                ("peak_bytes", ctypes.c_size_t)]
+                ("peak_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -338,7 +338,7 @@ class Server:
     continuous batching on `max_slots` streams under a device-memory budget.  simulate=True models
     the schedule on the host only (no device work; results carry no hologram)."""
 
-    def __init__(self, lut: Lut | None, hbm_budget_bytes: int, max_slots: int = 4,
+    def __init__(self, lut: Lut | None, hbm_budget_bytes: int, max_slots: int = 2,
                  simulate: bool = False, sim_ns_per_pixel: float = 0.0):
         self._lut = lut  # keeps the LUT alive while the server exists
         cfg = _ServerConfig(hbm_budget_bytes, max_slots, 1 if simulate else 0, sim_ns_per_pixel,

@@ -34,9 +34,12 @@ void clear_error();
 
 // Stream-ordered scratch: allocated from the device's default pool on `stream` and returned to
 // it on the same stream when the guard goes out of scope.
+// With an arena, allocations are carved (256-byte aligned) from that caller-owned device buffer
+// instead, and nothing is freed: work on `stream` orders the reuse of the arena.
 class Scratch {
   public:
     explicit Scratch(hipStream_t s) : stream_(s) {}
+    Scratch(hipStream_t s, void *arena, size_t cap) : stream_(s), arena_((char *)arena), cap_(cap) {}
     ~Scratch();
     // Returns CGH_OK or CGH_ENOMEM/CGH_EHIP; *p receives device memory of `bytes` bytes.
     int alloc(void **p, size_t bytes);
@@ -44,6 +47,8 @@ class Scratch {
   private:
     hipStream_t stream_;
     std::vector<void *> ptrs_;
+    char *arena_ = nullptr;
+    size_t cap_ = 0, used_ = 0;
 };
 
 // Keeps the default pool's memory cached between calls (release threshold = unlimited) and stops it
@@ -83,9 +88,18 @@ class ProfScope {
 // many bytes as (value, key) entries and need no keys, no LDS atomics and no fixed point.
 constexpr double kDenseGamma = 0.35;
 
+// On-chip tile buffer layout: block (r, c) of a tile starts at r * row_stride + c * block_stride.
+// The pads decide how the LDS banks of equal in-block codes of neighbouring blocks and block rows
+// line up; these values minimise the bank conflicts of the superposition's scattered atomic adds
+// (a model of the 64-lane adds over the kept entries of real tables, for 32 and 64 banks).
 __host__ __device__ constexpr int block_stride(int L)
 {
-    return (1 << (2 * L)) + ((1 << L) <= 16 ? (1 << L) : 0);
+    return L <= 2 ? (1 << (2 * L)) + (1 << L) : (1 << (2 * L)) + (1 << (L - 2));
+}
+
+__host__ __device__ constexpr int row_pad(int L)
+{
+    return L == 3 ? 32 : (L == 4 ? 8 : 0);
 }
 
 struct DepthDesc {
@@ -104,6 +118,10 @@ struct DepthDesc {
 // Dense layout (kept when gamma is large): every Haar block of a block row between the first and
 // the last block holding kept entries is stored whole (B*B coefficients, zeros where dropped),
 // block after block, so the blocks a tile needs from one table block row are one contiguous run.
+// Zero values stored after the dense tables: the superposition reads them in place of table blocks
+// that a pair does not cover, so every pair issues the same loads.
+constexpr int kDenseZero = 512;
+
 struct DenseRow {
     int32_t lo, hi;  // stored blocks [lo, hi) of this block row
     int32_t off;     // first coefficient of block lo, relative to the plane's dense_base
@@ -129,6 +147,7 @@ struct wasabi_lut {
     uint16_t *keys;                   // device
     bool dense;                       // dense layout present (used by the superposition)
     void *dense_values;               // device, same element type as values
+    int64_t dense_zero;               // first of kDenseZero zero values after the dense tables
     cgh::DenseRow *dense_rows;        // device
     size_t device_bytes;
 };
@@ -142,8 +161,9 @@ int validate_params(const wasabi_lut_params *prm);
 // pool for n points on an nx x ny window at origin (0, 0).
 int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny);
 
-// wasabi_hologram_fused at origin (0, 0), u contiguous, without plane pacing: for work that shares
-// the device with other streams, where the tiles of one launch cannot count on being co-resident.
+// wasabi_hologram_fused at origin (0, 0), u contiguous, without plane pacing (for work that shares
+// the device with other streams, where the tiles of one launch cannot count on being co-resident),
+// its scratch carved from `arena` (at least fused_scratch_bound bytes).
 int hologram_fused_shared(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int32_t nx,
-                          int32_t ny, void *u, hipStream_t s);
+                          int32_t ny, void *u, hipStream_t s, void *arena, size_t arena_bytes);
 }  // namespace cgh

@@ -501,14 +501,16 @@ int build_dense(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
         total += off;
     }
     const size_t vb = value_bytes(lut->prm.value_dtype);
-    hipError_t e1 = hipMalloc(&lut->dense_values, vb * (size_t)std::max<int64_t>(total, 1));
+    lut->dense_zero = total;
+    total += kDenseZero;
+    hipError_t e1 = hipMalloc(&lut->dense_values, vb * (size_t)total);
     hipError_t e2 = hipMalloc((void **)&lut->dense_rows, sizeof(DenseRow) * rows.size());
     if (e1 != hipSuccess || e2 != hipSuccess) {
         (void)hipGetLastError();
         return fail(CGH_ENOMEM, "dense LUT allocation of %lld coefficients failed", (long long)total);
     }
     lut->device_bytes += vb * (size_t)total + sizeof(DenseRow) * rows.size();
-    CGH_TRY_HIP(hipMemset(lut->dense_values, 0, vb * (size_t)std::max<int64_t>(total, 1)));
+    CGH_TRY_HIP(hipMemset(lut->dense_values, 0, vb * (size_t)total));
     CGH_TRY_HIP(hipMemcpy(lut->dense_rows, rows.data(), sizeof(DenseRow) * rows.size(), hipMemcpyHostToDevice));
     if (!jobs.empty()) {
         DenseJob *jd = nullptr;
@@ -632,6 +634,7 @@ wasabi_lut *new_lut(const wasabi_lut_params *prm)
     lut->values = nullptr;
     lut->keys = nullptr;
     lut->dense = false;
+    lut->dense_zero = 0;
     lut->dense_values = nullptr;
     lut->dense_rows = nullptr;
     lut->device_bytes = 0;

@@ -1,4 +1,5 @@
 // Error state, stream-ordered scratch and plane geometry of libcgh.so.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -29,6 +30,13 @@ Scratch::~Scratch()
 int Scratch::alloc(void **p, size_t bytes)
 {
     *p = nullptr;
+    if (arena_) {
+        const size_t b = std::max<size_t>((bytes + 255) & ~(size_t)255, 256);
+        if (used_ + b > cap_) return fail(CGH_ENOMEM, "scratch arena of %zu bytes exhausted", cap_);
+        *p = arena_ + used_;
+        used_ += b;
+        return CGH_OK;
+    }
     if (bytes == 0) bytes = 256;
     hipError_t e = hipMallocAsync(p, bytes, stream_);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {

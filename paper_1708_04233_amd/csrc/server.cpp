@@ -4,10 +4,13 @@
 // One scheduler thread per server owns every device call of the jobs: it admits the head of the
 // queue as soon as a slot (stream) is free and the job's bytes fit the budget, issues the job's
 // work on that slot's stream (upload through the slot's pinned staging buffer, quantise, fused
-// superposition + inverse, then an event), and polls the events of the running jobs; a finished
-// job gives back its slot and working memory, while its result stays charged to the budget until
-// the caller releases it.  Client calls (submit / wait / cancel / release / query) only touch host
-// state under the server's mutex, except release, which hands the result back to the pool.
+// superposition + inverse, then an event), and polls the events of the running jobs.
+// Memory: each slot keeps a device arena that holds a job's working memory (points, quantised
+// points, the superposition's scratch), grown when a larger job comes and given back when an idle
+// slot's arena is needed to admit a job; the result is allocated per job and stays charged to the
+// budget until the caller releases it.  The budget counts the arenas plus the held results, i.e.
+// the device memory the server holds.  Client calls (submit / wait / cancel / release / query)
+// only touch host state under the server's mutex, except release, which frees the result.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -42,7 +45,7 @@ struct ServerJob {
     int status = CGH_OK;
     int slot = -1;
     double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0, sim_end = 0, gpu_ms = 0;
-    void *d_pts = nullptr, *d_q = nullptr, *d_u = nullptr;
+    void *d_u = nullptr;
     hipStream_t result_stream = nullptr;  // stream the result was allocated on
 };
 
@@ -52,6 +55,9 @@ struct Slot {
     uint64_t ticket = 0;      // 0 = free
     void *pinned = nullptr;   // staging buffer of the uploads issued on this slot
     size_t pinned_cap = 0;
+    size_t arena_cap = 0;     // bytes of the slot's arena charged to the budget
+    void *arena = nullptr;    // the arena as allocated (at most arena_cap bytes; grown on issue)
+    size_t arena_real = 0;
 };
 
 // How often the scheduler looks at the running jobs' events while any job runs.
@@ -117,6 +123,19 @@ void free_result(cgh_server *S, ServerJob &j)
     j.result_held = false;
 }
 
+size_t round_up(size_t b)
+{
+    return (b + 255) & ~(size_t)255;
+}
+
+// Working memory of a job in its slot's arena.
+size_t work_bytes_of(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny)
+{
+    size_t b = round_up(sizeof(double) * 4 * (size_t)n) + round_up(sizeof(wasabi_point) * (size_t)n);
+    if (lut) b += (size_t)fused_scratch_bound(lut, n, nx, ny);
+    return b;
+}
+
 // Issue the job's device work on its slot's stream.  Called without the lock: the job and its
 // slot belong to the scheduler while the job runs.
 int issue(cgh_server *S, ServerJob &j, Slot &sl)
@@ -136,22 +155,26 @@ int issue(cgh_server *S, ServerJob &j, Slot &sl)
     }
     if (bytes) std::memcpy(sl.pinned, j.host.data(), bytes);
     CGH_TRY_HIP(hipEventRecord(sl.ev0, s));
-    if (j.n > 0) {
-        CGH_TRY_HIP(hipMallocAsync(&j.d_pts, bytes, s));
-        CGH_TRY_HIP(hipMallocAsync(&j.d_q, sizeof(wasabi_point) * (size_t)j.n, s));
+    if (sl.arena_real < sl.arena_cap) {
+        if (sl.arena) CGH_TRY_HIP(hipFreeAsync(sl.arena, s));
+        sl.arena = nullptr;
+        sl.arena_real = 0;
+        CGH_TRY_HIP(hipMallocAsync(&sl.arena, sl.arena_cap, s));
+        sl.arena_real = sl.arena_cap;
     }
     CGH_TRY_HIP(hipMallocAsync(&j.d_u, sizeof(float) * 2 * (size_t)j.nx * j.ny, s));
     j.result_stream = s;
+    // arena: device points | quantised points | superposition scratch
+    const size_t pts_bytes = round_up(bytes), q_bytes = round_up(sizeof(wasabi_point) * (size_t)j.n);
+    char *ar = (char *)sl.arena;
     if (j.n > 0) {
-        CGH_TRY_HIP(hipMemcpyAsync(j.d_pts, sl.pinned, bytes, hipMemcpyHostToDevice, s));
-        int rc = wasabi_quantize(lut, (const double *)j.d_pts, j.n, (wasabi_point *)j.d_q, s);
+        CGH_TRY_HIP(hipMemcpyAsync(ar, sl.pinned, bytes, hipMemcpyHostToDevice, s));
+        int rc = wasabi_quantize(lut, (const double *)ar, j.n, (wasabi_point *)(ar + pts_bytes), s);
         if (rc) return rc;
     }
-    int rc = hologram_fused_shared(lut, (const wasabi_point *)j.d_q, j.n, j.nx, j.ny, j.d_u, s);
+    int rc = hologram_fused_shared(lut, (const wasabi_point *)(ar + pts_bytes), j.n, j.nx, j.ny, j.d_u, s,
+                                   ar + pts_bytes + q_bytes, sl.arena_real - pts_bytes - q_bytes);
     if (rc) return rc;
-    if (j.d_pts) CGH_TRY_HIP(hipFreeAsync(j.d_pts, s));
-    if (j.d_q) CGH_TRY_HIP(hipFreeAsync(j.d_q, s));
-    j.d_pts = j.d_q = nullptr;
     CGH_TRY_HIP(hipEventRecord(sl.ev1, s));
     return CGH_OK;
 }
@@ -167,7 +190,6 @@ void retire(cgh_server *S, ServerJob &j, int status)
         else (void)hipGetLastError();
     }
     sl.ticket = 0;
-    S->used -= j.work_bytes;
     --S->st.running;
     std::vector<double>().swap(j.host);
     if (j.cancel || status != CGH_OK) {
@@ -178,25 +200,64 @@ void retire(cgh_server *S, ServerJob &j, int status)
     }
 }
 
+// Give back the arena of an idle slot.  Lock held; the enqueue does not block.
+void drop_arena(cgh_server *S, Slot &sl)
+{
+    if (sl.arena) (void)hipFreeAsync(sl.arena, sl.stream);
+    sl.arena = nullptr;
+    sl.arena_real = 0;
+    S->used -= sl.arena_cap;
+    sl.arena_cap = 0;
+}
+
+// Free slot for the queue head, or -1: the free slot with the largest arena, after giving back
+// the arenas of other idle slots if that is what makes the job fit.  Lock held.
+int pick_slot(cgh_server *S, const ServerJob &j)
+{
+    int best = -1;
+    size_t others = 0;
+    for (int i = 0; i < (int)S->slots.size(); ++i) {
+        const Slot &sl = S->slots[i];
+        if (sl.ticket) continue;
+        if (best < 0 || sl.arena_cap > S->slots[best].arena_cap) best = i;
+        others += sl.arena_cap;
+    }
+    if (best < 0) return -1;
+    others -= S->slots[best].arena_cap;
+    const size_t grow = j.work_bytes > S->slots[best].arena_cap ? j.work_bytes - S->slots[best].arena_cap : 0;
+    const size_t need = j.result_bytes + grow;
+    if (S->used + need <= S->cfg.hbm_budget_bytes) return best;
+    if (S->used - others + need > S->cfg.hbm_budget_bytes) return -1;
+    for (int i = 0; i < (int)S->slots.size() && S->used + need > S->cfg.hbm_budget_bytes; ++i)
+        if (i != best && S->slots[i].ticket == 0 && S->slots[i].arena_cap) drop_arena(S, S->slots[i]);
+    return best;
+}
+
 void admit(cgh_server *S, ServerJob &j, int slot, std::unique_lock<std::mutex> &lk)
 {
     j.state = JobState::Running;
     j.slot = slot;
     j.t_admit = S->now();
-    S->used += j.work_bytes + j.result_bytes;
+    Slot &arena_slot = S->slots[slot];
+    if (j.work_bytes > arena_slot.arena_cap) {
+        S->used += j.work_bytes - arena_slot.arena_cap;
+        arena_slot.arena_cap = j.work_bytes;
+    }
+    S->used += j.result_bytes;
     j.result_held = true;
     S->st.peak_bytes = std::max(S->st.peak_bytes, S->used);
     ++S->st.running;
     S->st.max_running = std::max(S->st.max_running, S->st.running);
     Slot &sl = S->slots[slot];
     sl.ticket = j.ticket;
-    j.t_start = S->now();
+    j.t_start = j.t_admit;
     if (S->cfg.simulate) {
         j.sim_end = j.t_start + S->cfg.sim_ns_per_pixel * 1e-9 * (double)j.nx * (double)j.ny;
         return;
     }
     lk.unlock();
     const int rc = issue(S, j, sl);
+    j.t_start = S->now();
     if (rc) {
         // Nothing behind the failure will run; wait for what was enqueued before giving the
         // staging buffer and memory back.  The slot stays taken meanwhile.
@@ -205,9 +266,6 @@ void admit(cgh_server *S, ServerJob &j, int slot, std::unique_lock<std::mutex> &
     }
     lk.lock();
     if (rc) {
-        if (j.d_pts) (void)hipFreeAsync(j.d_pts, sl.stream);
-        if (j.d_q) (void)hipFreeAsync(j.d_q, sl.stream);
-        j.d_pts = j.d_q = nullptr;
         j.t_done = S->now();
         retire(S, j, rc);
     }
@@ -242,13 +300,8 @@ void scheduler(cgh_server *S)
             // 2. admissions, strictly in submission order
             while (!S->queue.empty()) {
                 ServerJob &j = *S->jobs.at(S->queue.front());
-                int slot = -1;
-                for (int i = 0; i < (int)S->slots.size(); ++i)
-                    if (S->slots[i].ticket == 0) {
-                        slot = i;
-                        break;
-                    }
-                if (slot < 0 || S->used + j.work_bytes + j.result_bytes > S->cfg.hbm_budget_bytes) break;
+                const int slot = pick_slot(S, j);
+                if (slot < 0) break;
                 S->queue.pop_front();
                 admit(S, j, slot, lk);
             }
@@ -353,8 +406,7 @@ extern "C" int cgh_server_submit(cgh_server *S, const cgh_job *job, uint64_t *ti
     j->nx = job->nx;
     j->ny = job->ny;
     j->result_bytes = sizeof(float) * 2 * (size_t)job->nx * job->ny;
-    j->work_bytes = (sizeof(double) * 4 + sizeof(wasabi_point)) * (size_t)job->n;
-    if (S->cfg.lut) j->work_bytes += (size_t)fused_scratch_bound(S->cfg.lut, job->n, job->nx, job->ny);
+    j->work_bytes = work_bytes_of(S->cfg.lut, job->n, job->nx, job->ny);
     if (j->work_bytes + j->result_bytes > S->cfg.hbm_budget_bytes)
         return fail(CGH_ENOMEM, "job needs %zu bytes, budget is %zu", j->work_bytes + j->result_bytes,
                     S->cfg.hbm_budget_bytes);
@@ -460,6 +512,8 @@ extern "C" int cgh_server_query(cgh_server *S, cgh_server_stats *out)
     *out = S->st;
     out->queued = (int64_t)S->queue.size();
     out->bytes_in_use = S->used;
+    out->arena_bytes = 0;
+    for (const Slot &sl : S->slots) out->arena_bytes += sl.arena_cap;
     return CGH_OK;
 }
 
@@ -497,6 +551,7 @@ extern "C" int cgh_server_destroy(cgh_server *S)
             (void)hipEventDestroy(sl.ev0);
             (void)hipEventDestroy(sl.ev1);
             if (sl.pinned) (void)hipHostFree(sl.pinned);
+            if (sl.arena) (void)hipFree(sl.arena);
         }
     }
     delete S;

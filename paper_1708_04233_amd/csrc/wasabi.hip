@@ -230,22 +230,31 @@ __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_po
                                                                  int L, TileGeom g, int nwg,
                                                                  const int64_t *moff, int32_t *list)
 {
-    __shared__ int cnt[kMaxLdsTiles];
+    // next free list position of this workgroup's segment in every tile's list (all loads in
+    // flight at once, so the point loop below only reads on-chip memory)
+    __shared__ int64_t pos[kMaxLdsTiles];
+    __shared__ int fp[kChunk][4];
     const int ntiles = g.ntx * g.nty;
-    for (int i = threadIdx.x; i < ntiles; i += kChunk) cnt[i] = 0;
-    __syncthreads();
+    for (int i = threadIdx.x; i < ntiles; i += kChunk) pos[i] = moff[(int64_t)i * nwg + blockIdx.x];
     const int64_t j0 = (int64_t)blockIdx.x * kChunk;
     const int np = (int)min((int64_t)kChunk, n - j0);
+    {
+        int ty0 = 0, ty1 = 0, tx0 = 0, tx1 = 0;
+        if (threadIdx.x < np && !footprint(pts[j0 + threadIdx.x], desc, n_depth, L, g, ty0, ty1, tx0, tx1))
+            ty0 = ty1 = tx0 = tx1 = 0;
+        fp[threadIdx.x][0] = ty0;
+        fp[threadIdx.x][1] = ty1;
+        fp[threadIdx.x][2] = tx0;
+        fp[threadIdx.x][3] = tx1;
+    }
+    __syncthreads();
+    // points in order (the lists stay in sorted-point order); the threads share a point's tiles
     for (int q = 0; q < np; ++q) {
-        const int64_t j = j0 + q;
-        int ty0, ty1, tx0, tx1;
-        if (!footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) continue;
+        const int ty0 = fp[q][0], ty1 = fp[q][1], tx0 = fp[q][2], tx1 = fp[q][3];
         const int w = tx1 - tx0, cells = (ty1 - ty0) * w;
         for (int c = threadIdx.x; c < cells; c += kChunk) {
             const int t = (ty0 + c / w) * g.ntx + tx0 + c % w;
-            const int rank = cnt[t];
-            cnt[t] = rank + 1;
-            list[moff[(int64_t)t * nwg + blockIdx.x] + rank] = (int32_t)j;
+            list[pos[t]++] = (int32_t)(j0 + q);
         }
         __syncthreads();
     }
@@ -325,6 +334,7 @@ struct TileArgs {
     float2 *out;       // MODE_PSI: Mallat field (row stride nx); otherwise pixels (row stride ld)
     int64_t ld;
     const void *dense;          // dense layout values (or NULL)
+    int64_t dense_zero;         // first of kDenseZero zero values in `dense`
     const DenseRow *dense_rows; // dense layout block-row spans
     int n_depth;
     int *plane_done;            // plane pacing: tiles that finished plane d (NULL = off)
@@ -336,7 +346,7 @@ struct TileShape {
     static constexpr int B = 1 << L;
     static constexpr int TB = kT / B;             // blocks per tile side
     static constexpr int BS = block_stride(L);    // LDS floats per block
-    static constexpr int ROW = TB * BS;           // LDS floats per block row
+    static constexpr int ROW = TB * BS + row_pad(L);  // LDS floats per block row
     static constexpr int N = TB * ROW;            // LDS floats per plane (re or im)
 };
 
@@ -353,6 +363,13 @@ __device__ inline float2 load_value(const void *values, int64_t i)
         return make_float2((float)lo, (float)hi);
     }
     return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
+// Address of element i of a value array (FP32: float2 elements; FP16/BF16: packed 32-bit pairs).
+template <int VT>
+__device__ inline const void *value_at(const void *values, int64_t i)
+{
+    return (const char *)values + i * (VT == CGH_F32 ? 8 : 4);
 }
 
 // Moves the tile's coefficients between LDS and the window's Mallat layout (rows of nx).
@@ -488,8 +505,50 @@ __device__ inline void add_pair(int *are, int *aim, const void *values, const ui
                                 int rcount)
 {
     using S = TileShape<L>;
-    constexpr int U = 4;
     const int lane = threadIdx.x & 63;
+    if constexpr (S::TB <= 8) {
+        // The rows' entry ranges are walked as one flat range of `total` entries (row r owns
+        // [ex_r, ex_r + count_r)), 64 lanes x 2 entries per step, all loads of a step issued
+        // before its adds; lanes past the end re-read the last entry and add 0 to their own word.
+        int ex[S::TB], off[S::TB];
+        int total = 0;
+#pragma unroll
+        for (int r = 0; r < S::TB; ++r) {
+            ex[r] = total;
+            off[r] = __builtin_amdgcn_readlane(rstart, r) - total;
+            total += __builtin_amdgcn_readlane(rcount, r);  // 0 for lanes >= nrows
+        }
+        for (int c = 0; c < total; c += 128) {
+            float2 v[2];
+            int key[2], drow[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = min(c + 64 * u + lane, total - 1);
+                int o = off[0];
+                drow[u] = 0;
+#pragma unroll
+                for (int r = 1; r < S::TB; ++r)
+                    if (e >= ex[r]) {
+                        o = off[r];
+                        drow[u] = r * S::ROW;
+                    }
+                const int64_t idx = (int64_t)eb + e + o;
+                v[u] = load_value<VT>(values, idx);
+                key[u] = keys[idx];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const bool on = c + 64 * u + lane < total;
+                const double sa = on ? scaled_amp : 0.0;
+                const int at = on ? dst0 + drow[u] + key[u] : S::N + lane;
+                atomicAdd(&are[at], to_fixed(v[u].x, sa));
+                atomicAdd(&aim[at], to_fixed(v[u].y, sa));
+            }
+        }
+        (void)nrows;
+        return;
+    }
+    constexpr int U = 4;
     for (int r = 0; r < nrows; ++r) {
         const int rs = __builtin_amdgcn_readlane(rstart, r);
         const int rc = __builtin_amdgcn_readlane(rcount, r);
@@ -525,9 +584,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
 {
     using S = TileShape<L>;
     constexpr int NW = kTileThreads / 64;
-    __shared__ int acc[2 * S::N];  // fixed-point re plane, then im plane
+    // fixed-point re plane, then im plane, each followed by 64 words that take the (zero) adds of
+    // lanes past the end of a range, one word per lane so that they do not collide
+    __shared__ int acc[2 * (S::N + 64)];
     __shared__ double red[kTileThreads / 64];
-    int *are = acc, *aim = acc + S::N;
+    int *are = acc, *aim = acc + S::N + 64;
     const int tile = blockIdx.x;
     const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
@@ -544,7 +605,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     }
     for (int o = 32; o > 0; o >>= 1) bound += __shfl_down(bound, o);
     if (lane == 0) red[wave] = bound;
-    for (int i = threadIdx.x; i < 2 * S::N; i += kTileThreads) acc[i] = 0;
+    for (int i = threadIdx.x; i < 2 * (S::N + 64); i += kTileThreads) acc[i] = 0;
     __syncthreads();
     bound = 0.0;
     for (int w = 0; w < NW; ++w) bound += red[w];
@@ -658,26 +719,21 @@ void dense_tile_kernel(TileArgs a)
     const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
     const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
 
-    // the lane's coefficients: c_i = 512 w + 64 i + lane -> tile block b_i = c_i / BB, code_i
-    int tbr[PER], tbc[PER], code[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int c = wave * 512 + i * 64 + lane;
-        const int b = c / BB;
-        tbr[i] = b / S::TB;
-        tbc[i] = b % S::TB;
-        code[i] = c % BB;
-    }
+    // the lane's coefficient i: c = 512 w + 64 i + lane -> tile block b = c / BB (block row b / TB,
+    // column b % TB), code c % BB.  Recomputed where needed rather than held in registers.
+    auto tbr_of = [&](int i) { return ((wave * 512 + i * 64 + lane) / BB) / S::TB; };
+    auto tbc_of = [&](int i) { return ((wave * 512 + i * 64 + lane) / BB) % S::TB; };
+    auto code_of = [&](int i) { return (wave * 512 + i * 64 + lane) % BB; };
     float are[PER], aim[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) are[i] = aim[i] = 0.0f;
 
     if (BB >= 64) {
         // For L >= 3 the wave's coefficients lie in one tile block row (tr) and tile block columns
-        // tbc[i]; per pair only one table block row (tr - obr) is involved.  Lane k resolves pair k
+        // tbc_of(i); per pair only one table block row (tr - obr) is involved.  Lane k resolves pair k
         // of each 64-pair batch up to the address of its first coefficient (one parallel pass over
         // the dependent loads), then the wave walks the pairs.
-        const int tr = tbr[0];
+        const int tr = tbr_of(0);
         auto run = [&](int64_t q0, int64_t q1) {
             for (int64_t pb = q0; pb < q1; pb += 64) {
                 const int64_t pk = pb + lane;
@@ -710,10 +766,10 @@ void dense_tile_kernel(TileArgs a)
                     float2 v[PER];
 #pragma unroll
                     for (int i = 0; i < PER; ++i)
-                        if (tbc[i] >= clo && tbc[i] < chi) v[i] = load_value<VT>(a.dense, b0 + (int64_t)tbc[i] * BB + code[i]);
+                        if (tbc_of(i) >= clo && tbc_of(i) < chi) v[i] = load_value<VT>(a.dense, b0 + (int64_t)tbc_of(i) * BB + code_of(i));
 #pragma unroll
                     for (int i = 0; i < PER; ++i)
-                        if (tbc[i] >= clo && tbc[i] < chi) {
+                        if (tbc_of(i) >= clo && tbc_of(i) < chi) {
                             are[i] = fmaf(amp, v[i].x, are[i]);
                             aim[i] = fmaf(amp, v[i].y, aim[i]);
                         }
@@ -803,11 +859,11 @@ void dense_tile_kernel(TileArgs a)
                 const DenseRow *rows = a.dense_rows + dd.rows_base;
 #pragma unroll
                 for (int i = 0; i < PER; ++i) {
-                    const int br = tbr[i] - obr, bc = tbc[i] - obc;
+                    const int br = tbr_of(i) - obr, bc = tbc_of(i) - obc;
                     if (br < dd.br0 || br >= dd.br1) continue;
                     const DenseRow row = rows[br];
                     if (bc < row.lo || bc >= row.hi) continue;
-                    const float2 v = load_value<VT>(a.dense, base + row.off + (int64_t)(bc - row.lo) * BB + code[i]);
+                    const float2 v = load_value<VT>(a.dense, base + row.off + (int64_t)(bc - row.lo) * BB + code_of(i));
                     are[i] = fmaf(amp, v.x, are[i]);
                     aim[i] = fmaf(amp, v.y, aim[i]);
                 }
@@ -819,7 +875,7 @@ void dense_tile_kernel(TileArgs a)
     float *sre = sbuf, *sim = sbuf + S::N;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int at = tbr[i] * S::ROW + tbc[i] * S::BS + code[i];
+        const int at = tbr_of(i) * S::ROW + tbc_of(i) * S::BS + code_of(i);
         sre[at] = are[i];
         sim[at] = aim[i];
     }
@@ -1061,6 +1117,7 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.out = out;
     a.ld = ld;
     a.dense = lut ? lut->dense_values : nullptr;
+    a.dense_zero = lut ? lut->dense_zero : 0;
     a.dense_rows = lut ? lut->dense_rows : nullptr;
     a.n_depth = lut ? lut->prm.n_depth : 0;
     a.plane_done = nullptr;
@@ -1103,12 +1160,13 @@ int64_t resident_capacity(int L, int vt, int mode)
 
 int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox,
                    int64_t oy, int32_t nx, int32_t ny, void *out, int64_t ld, int mode,
-                   hipStream_t s, bool allow_pace = true)
+                   hipStream_t s, bool allow_pace = true, Scratch *ext = nullptr)
 {
     int rc = prepare_pool();
     if (rc) return rc;
     const TileGeom g = make_geom(ox, oy, nx, ny);
-    Scratch sc(s);
+    Scratch local(s);
+    Scratch &sc = ext ? *ext : local;
     int64_t *tile_off;
     int32_t *tile_pts;
     const wasabi_point *sorted;
@@ -1191,11 +1249,12 @@ int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_
 }
 
 int hologram_fused_shared(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int32_t nx,
-                          int32_t ny, void *u, hipStream_t s)
+                          int32_t ny, void *u, hipStream_t s, void *arena, size_t arena_bytes)
 {
     int rc = check_common(lut, pts, n, 0, 0, nx, ny, u);
     if (rc) return rc;
-    return superpose_impl(lut, pts, n, 0, 0, nx, ny, u, nx, MODE_FUSED, s, false);
+    Scratch sc(s, arena, arena_bytes);
+    return superpose_impl(lut, pts, n, 0, 0, nx, ny, u, nx, MODE_FUSED, s, false, &sc);
 }
 
 }  // namespace cgh

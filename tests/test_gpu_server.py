@@ -60,10 +60,10 @@ def test_mix_equals_alone(request, which):
     jobs = mix(100, [1024, 2048, 4096, 1024, 2048, 1024, 8192, 1024],
                [3000, 20000, 5000, 1000, 60000, 0, 15000, 2500])
     ref = [alone(lut, side, p) for side, p in jobs]
-    out, st = run_mix(lut, jobs, 64 << 30, 4)
+    out, st = run_mix(lut, jobs, 64 << 30, 2)
     assert st["completed"] == len(jobs) and st["failed"] == 0
-    assert st["max_running"] >= 2          # jobs overlapped on the device
-    assert st["bytes_in_use"] == 0
+    assert st["max_running"] == 2          # jobs overlapped on the device
+    assert st["bytes_in_use"] == st["arena_bytes"]   # results released; the slots keep arenas
     for (r, u), want, (side, p) in zip(out, ref, jobs):
         if len(p) == 0:
             assert torch.count_nonzero(u).item() == 0
@@ -73,13 +73,29 @@ def test_mix_equals_alone(request, which):
         assert r["t_submit"] <= r["t_admit"] <= r["t_start"] <= r["t_done"]
 
 
-def test_tight_budget_runs_one_at_a_time(lut16):
-    jobs = mix(300, [2048, 1024, 2048, 1024], [8000, 4000, 3000, 9000])
+def job_bytes(lut, side, pts):
+    """Bytes the server charges for one job: its peak alone on an otherwise idle server."""
+    with cgh.Server(lut, 1 << 40, max_slots=1) as s:
+        t = s.submit(pts, side, side)
+        s.wait(t, 60000)
+        b = s.stats()["peak_bytes"]
+        s.release(t)
+    return b
+
+
+def test_tight_budget_admission(lut16):
+    """Budget = the largest job's bytes: jobs that do not fit together never run together, and every
+    result is still the job's hologram."""
+    jobs = mix(300, [2048, 1024, 2048, 1024, 2048], [8000, 4000, 3000, 9000, 500])
     ref = [alone(lut16, side, p) for side, p in jobs]
-    budget = 8 * 2048 * 2048 + (200 << 20)   # one 2048^2 job with its scratch, not two
-    out, st = run_mix(lut16, jobs, budget, 4)
+    need = [job_bytes(lut16, side, p) for side, p in jobs]
+    budget = max(need)
+    out, st = run_mix(lut16, jobs, budget, 2)
     assert st["peak_bytes"] <= budget
-    assert st["max_running"] <= 2
+    for i in range(len(jobs)):
+        for j in range(i + 1, len(jobs)):
+            if need[i] + need[j] > budget:   # j was admitted only after i's result was released
+                assert out[j][0]["t_admit"] >= out[i][0]["t_done"]
     for (r, u), want in zip(out, ref):
         assert rel(u, want) <= TOL
 

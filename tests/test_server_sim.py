@@ -30,7 +30,9 @@ def result_bytes(side):
 
 
 def work_bytes(n):
-    return 48 * n  # device points + quantised points (no LUT: no superposition scratch)
+    """Arena bytes of a job without a LUT: device points + quantised points, 256-byte granules."""
+    r = lambda b: (b + 255) // 256 * 256
+    return r(32 * n) + r(16 * n)
 
 
 def test_all_jobs_complete_with_ordered_times(lib):
@@ -45,7 +47,8 @@ def test_all_jobs_complete_with_ordered_times(lib):
             s.release(t)
         st = s.stats()
         assert st["submitted"] == 12 and st["completed"] == 12 and st["canceled"] == 0
-        assert st["queued"] == 0 and st["running"] == 0 and st["bytes_in_use"] == 0
+        assert st["queued"] == 0 and st["running"] == 0
+        assert st["bytes_in_use"] == st["arena_bytes"] > 0      # only the slots' arenas remain
         assert 1 <= st["max_running"] <= 4
 
 
@@ -84,9 +87,11 @@ def test_results_stay_charged_until_release(lib):
     with server(1 << 40) as s:
         t = s.submit(pts(7), side, side)
         s.wait(t, 5000)
-        assert s.stats()["bytes_in_use"] == result_bytes(side)
+        st = s.stats()
+        assert st["arena_bytes"] == work_bytes(7)
+        assert st["bytes_in_use"] == result_bytes(side) + work_bytes(7)
         s.release(t)
-        assert s.stats()["bytes_in_use"] == 0
+        assert s.stats()["bytes_in_use"] == work_bytes(7)      # the slot keeps its arena
 
 
 def test_unreleased_results_block_admission(lib):
@@ -102,6 +107,45 @@ def test_unreleased_results_block_admission(lib):
         s.release(a)
         assert s.wait(b, 5000)["status"] == cgh.CGH_OK
         s.release(b)
+
+
+def test_idle_arenas_give_way(lib):
+    """A job that fits only if idle slots give back their arenas is admitted after they do."""
+    big = work_bytes(400_000)                          # 19.2 MB arena
+    budget = 2 * result_bytes(64) + big + 4096         # one arena of `big`, two results
+    with server(budget, slots=2) as s:
+        a = s.submit(pts(400_000), 64, 64)             # slot 0 grows to `big`
+        s.wait(a, 5000)
+        s.release(a)
+        b = s.submit(pts(10), 64, 64)                  # reuses slot 0's arena
+        s.wait(b, 5000)
+        s.release(b)
+        assert s.stats()["arena_bytes"] == big
+        t1 = s.submit(pts(400_000), 64, 64)
+        t2 = s.submit(pts(400_000), 64, 64)            # needs slot 0's arena: runs after t1
+        r1, r2 = s.wait(t1, 5000), s.wait(t2, 5000)
+        assert r2["t_admit"] >= r1["t_done"]
+        assert s.stats()["peak_bytes"] <= budget
+        s.release(t1)
+        s.release(t2)
+
+
+def test_idle_arena_dropped_to_admit(lib):
+    """An idle slot gives its arena back when a larger job needs the room."""
+    big, bigger = work_bytes(400_000), work_bytes(600_000)
+    budget = 2 * big + 2 * result_bytes(64) + 4096
+    with server(budget, slots=2, ns=10_000.0) as s:        # 64^2 -> ~40 ms: a and b overlap
+        a, b = s.submit(pts(400_000), 64, 64), s.submit(pts(400_000), 64, 64)
+        s.wait(a, 5000)
+        s.wait(b, 5000)
+        s.release(a)
+        s.release(b)
+        assert s.stats()["arena_bytes"] == 2 * big         # both slots grew
+        c = s.submit(pts(600_000), 64, 64)                 # fits only without the other arena
+        assert s.wait(c, 5000)["status"] == cgh.CGH_OK
+        st = s.stats()
+        assert st["arena_bytes"] == bigger and st["peak_bytes"] <= budget
+        s.release(c)
 
 
 def test_oversized_job_rejected(lib):
@@ -221,4 +265,4 @@ def test_submit_from_many_threads(lib):
             assert s.wait(t, 10000)["status"] == cgh.CGH_OK
             s.release(t)
         st = s.stats()
-        assert st["completed"] == 100 and st["bytes_in_use"] == 0
+        assert st["completed"] == 100 and st["bytes_in_use"] == st["arena_bytes"]
