@@ -399,9 +399,12 @@ def run_large(args, torch, cgh):
                "lut_entries": int(info["total_entries"]), "kernels_ms": kern}
         t_tile = kern.get("tile_fused", ms) * 1e-3
         algo = 8 * nx * ny + int(info["device_bytes"]) + 16 * n
-        res["roofline"] = {"kernel": "tile_fused", "bound": "hbm", "achieved": round(algo / t_tile / 1e9, 1),
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(algo / t_tile / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": algo}
+        symbol = "%s<%d, %d, 1>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt)
+        res["roofline"] = {"kernel": "tile_fused", "symbol": symbol, "bound": "hbm",
+                           "achieved": round(algo / t_tile / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(algo / t_tile / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic": counter_traffic("%s@%.2f" % (w["name"], g), symbol),
+                           "algorithmic_bytes": algo}
         if g == w["gamma"]:
             # the paper's procedure: sub-holograms (8192^2 for the 65536^2 case) superposed into a
             # wavelet field and inverted into their part of the hologram
