@@ -36,9 +36,11 @@ struct TileGeom {
     int64_t ox, oy;    // window origin, global pixels
     int32_t nx, ny;    // window size
     int32_t ntx, nty;  // tiles per row / column
+    int32_t cell;      // point lists are kept per cell of cell x cell pixels (a square of tiles)
+    int32_t nlx, nly;  // list cells per row / column
 };
 
-// Tiles touched by the occupied part of point p's table; false if none.
+// List cells touched by the occupied part of point p's table; false if none.
 __device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, int n_depth, int L,
                                  const TileGeom &g, int &ty0, int &ty1, int &tx0, int &tx1)
 {
@@ -51,10 +53,10 @@ __device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, i
     const int64_t r0 = r_org + d.br0 * B, r1 = r_org + d.br1 * B;
     const int64_t c0 = c_org + d.bc0 * B, c1 = c_org + d.bc1 * B;
     if (r1 <= 0 || c1 <= 0 || r0 >= g.ny || c0 >= g.nx) return false;
-    ty0 = (int)(max(r0, (int64_t)0) / kT);
-    ty1 = (int)((min(r1, (int64_t)g.ny) - 1) / kT) + 1;
-    tx0 = (int)(max(c0, (int64_t)0) / kT);
-    tx1 = (int)((min(c1, (int64_t)g.nx) - 1) / kT) + 1;
+    ty0 = (int)(max(r0, (int64_t)0) / g.cell);
+    ty1 = (int)((min(r1, (int64_t)g.ny) - 1) / g.cell) + 1;
+    tx0 = (int)(max(c0, (int64_t)0) / g.cell);
+    tx1 = (int)((min(c1, (int64_t)g.nx) - 1) / g.cell) + 1;
     return true;
 }
 
@@ -137,14 +139,14 @@ __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point 
     }
 }
 
-// ---- per-tile point lists (counting sort by tile) -------------------------------------------
+// ---- per-cell point lists (counting sort by list cell; a cell is a square of tiles) -------------------------------------------
 template <bool LDS>
 __global__ __launch_bounds__(256) void bin_count_kernel(const wasabi_point *pts, int64_t n,
                                                         const DepthDesc *desc, int n_depth, int L,
                                                         TileGeom g, int32_t *counts)
 {
     __shared__ int hist[LDS ? kMaxLdsTiles : 1];
-    const int ntiles = g.ntx * g.nty;
+    const int ntiles = g.nlx * g.nly;
     if (LDS) {
         for (int i = threadIdx.x; i < ntiles; i += 256) hist[i] = 0;
         __syncthreads();
@@ -154,8 +156,8 @@ __global__ __launch_bounds__(256) void bin_count_kernel(const wasabi_point *pts,
     if (j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) {
         for (int ty = ty0; ty < ty1; ++ty)
             for (int tx = tx0; tx < tx1; ++tx) {
-                if (LDS) atomicAdd(&hist[ty * g.ntx + tx], 1);
-                else atomicAdd(&counts[(int64_t)ty * g.ntx + tx], 1);
+                if (LDS) atomicAdd(&hist[ty * g.nlx + tx], 1);
+                else atomicAdd(&counts[(int64_t)ty * g.nlx + tx], 1);
             }
     }
     if (LDS) {
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
 {
     __shared__ int cnt[LDS ? kMaxLdsTiles : 1];
     __shared__ unsigned long long base[LDS ? kMaxLdsTiles : 1];
-    const int ntiles = g.ntx * g.nty;
+    const int ntiles = g.nlx * g.nly;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int ty0 = 0, ty1 = 0, tx0 = 0, tx1 = 0;
     const bool has = j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1);
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
         __syncthreads();
         if (has)
             for (int ty = ty0; ty < ty1; ++ty)
-                for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&cnt[ty * g.ntx + tx], 1);
+                for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&cnt[ty * g.nlx + tx], 1);
         __syncthreads();
         for (int i = threadIdx.x; i < ntiles; i += 256) {
             if (cnt[i]) base[i] = atomicAdd(&cursor[i], (unsigned long long)cnt[i]);
@@ -193,10 +195,10 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
     if (has)
         for (int ty = ty0; ty < ty1; ++ty)
             for (int tx = tx0; tx < tx1; ++tx) {
-                const int t = ty * g.ntx + tx;
+                const int t = ty * g.nlx + tx;
                 unsigned long long slot;
                 if (LDS) slot = base[t] + (unsigned long long)atomicAdd(&cnt[t], 1);
-                else slot = atomicAdd(&cursor[(int64_t)ty * g.ntx + tx], 1ull);
+                else slot = atomicAdd(&cursor[(int64_t)ty * g.nlx + tx], 1ull);
                 list[slot] = (int32_t)j;
             }
 }
@@ -213,14 +215,14 @@ __global__ __launch_bounds__(kChunk) void bin_count_matrix_kernel(const wasabi_p
                                                                   int32_t *mat)
 {
     __shared__ int hist[kMaxLdsTiles];
-    const int ntiles = g.ntx * g.nty;
+    const int ntiles = g.nlx * g.nly;
     for (int i = threadIdx.x; i < ntiles; i += kChunk) hist[i] = 0;
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * kChunk + threadIdx.x;
     int ty0, ty1, tx0, tx1;
     if (j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1))
         for (int ty = ty0; ty < ty1; ++ty)
-            for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&hist[ty * g.ntx + tx], 1);
+            for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&hist[ty * g.nlx + tx], 1);
     __syncthreads();
     for (int i = threadIdx.x; i < ntiles; i += kChunk) mat[(int64_t)i * nwg + blockIdx.x] = hist[i];
 }
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_po
     // flight at once, so the point loop below only reads on-chip memory)
     __shared__ int64_t pos[kMaxLdsTiles];
     __shared__ int fp[kChunk][4];
-    const int ntiles = g.ntx * g.nty;
+    const int ntiles = g.nlx * g.nly;
     for (int i = threadIdx.x; i < ntiles; i += kChunk) pos[i] = moff[(int64_t)i * nwg + blockIdx.x];
     const int64_t j0 = (int64_t)blockIdx.x * kChunk;
     const int np = (int)min((int64_t)kChunk, n - j0);
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_po
         const int ty0 = fp[q][0], ty1 = fp[q][1], tx0 = fp[q][2], tx1 = fp[q][3];
         const int w = tx1 - tx0, cells = (ty1 - ty0) * w;
         for (int c = threadIdx.x; c < cells; c += kChunk) {
-            const int t = (ty0 + c / w) * g.ntx + tx0 + c % w;
+            const int t = (ty0 + c / w) * g.nlx + tx0 + c % w;
             list[pos[t]++] = (int32_t)(j0 + q);
         }
         __syncthreads();
@@ -593,7 +595,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int tbh = th >> L, tbw = tw >> L;
-    const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
+    const int sup = a.g.cell / kT, lst = (ty / sup) * a.g.nlx + tx / sup;  // the tile's list cell
+    const int64_t p0 = a.tile_off[lst], p1 = a.tile_off[lst + 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
 
@@ -716,7 +719,8 @@ void dense_tile_kernel(TileArgs a)
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t p0 = a.tile_off[tile], p1 = a.tile_off[tile + 1];
+    const int sup = a.g.cell / kT, lst = (ty / sup) * a.g.nlx + tx / sup;  // the tile's list cell
+    const int64_t p0 = a.tile_off[lst], p1 = a.tile_off[lst + 1];
     const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
 
     // the lane's coefficient i: c = 512 w + 64 i + lane -> tile block b = c / BB (block row b / TB,
@@ -912,7 +916,23 @@ TileGeom make_geom(int64_t ox, int64_t oy, int32_t nx, int32_t ny)
     g.ny = ny;
     g.ntx = (nx + kT - 1) / kT;
     g.nty = (ny + kT - 1) / kT;
+    g.cell = kT;
+    g.nlx = g.ntx;
+    g.nly = g.nty;
     return g;
+}
+
+// Point lists per tile while there are at most kMaxLdsTiles tiles; beyond that per square of
+// 2 x 2 or 4 x 4 tiles (the smallest that gives at most kMaxLdsTiles lists, 4 x 4 at most).  A
+// tile then walks its cell's list and skips the points that miss it: each point goes to far fewer
+// lists (binning is per (point, list) pair) at the price of a few more pairs per tile.
+void choose_lists(TileGeom &g)
+{
+    int sup = 1;
+    while (sup < 4 && (int64_t)((g.ntx + sup - 1) / sup) * ((g.nty + sup - 1) / sup) > kMaxLdsTiles) sup *= 2;
+    g.cell = kT * sup;
+    g.nlx = (g.ntx + sup - 1) / sup;
+    g.nly = (g.nty + sup - 1) / sup;
 }
 
 int check_window(int L, int64_t ox, int64_t oy, int32_t nx, int32_t ny)
@@ -955,12 +975,12 @@ int sort_bands(const wasabi_lut *lut, const TileGeom &g)
     return nyb;
 }
 
-// (tile, point) pairs the lists can hold: every point meets at most per_point tiles.
+// (list cell, point) pairs the lists can hold: every point meets at most per_point cells.
 int64_t pair_bound(const wasabi_lut *lut, int64_t n, const TileGeom &g)
 {
-    const int64_t ntiles = (int64_t)g.ntx * g.nty;
-    const int64_t per_side = (lut->max_span_px + kT - 1) / kT + 1;
-    const int64_t per_point = std::min<int64_t>(per_side * per_side, ntiles);
+    const int64_t nlists = (int64_t)g.nlx * g.nly;
+    const int64_t per_side = (lut->max_span_px + g.cell - 1) / g.cell + 1;
+    const int64_t per_point = std::min<int64_t>(per_side * per_side, nlists);
     return std::max<int64_t>(n * per_point, 1);
 }
 
@@ -975,7 +995,7 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
                Scratch &sc, hipStream_t s, const wasabi_point **sorted_out,
                int64_t **tile_off_out, int32_t **tile_pts_out, bool *ordered_out)
 {
-    const int64_t ntiles = (int64_t)g.ntx * g.nty;
+    const int64_t ntiles = (int64_t)g.nlx * g.nly;  // lists
     const int64_t bound = pair_bound(lut, n, g);
     const int nd = lut->prm.n_depth, L = lut->L;
     SortKey key;
@@ -1164,7 +1184,8 @@ int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, in
 {
     int rc = prepare_pool();
     if (rc) return rc;
-    const TileGeom g = make_geom(ox, oy, nx, ny);
+    TileGeom g = make_geom(ox, oy, nx, ny);
+    choose_lists(g);
     Scratch local(s);
     Scratch &sc = ext ? *ext : local;
     int64_t *tile_off;
@@ -1231,8 +1252,9 @@ int idwt_impl(const void *psi, int32_t nx, int32_t ny, int32_t levels, void *u, 
 
 int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny)
 {
-    const TileGeom g = make_geom(0, 0, nx, ny);
-    const int64_t ntiles = (int64_t)g.ntx * g.nty;
+    TileGeom g = make_geom(0, 0, nx, ny);
+    choose_lists(g);
+    const int64_t ntiles = (int64_t)g.nlx * g.nly;  // lists
     const int64_t nbins = (int64_t)lut->prm.n_depth * sort_bands(lut, g) + 1;
     auto r = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
     auto scan = [&](int64_t count) { return r(8 * ((count + 1023) / 1024)); };
