@@ -262,6 +262,25 @@ __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_po
     }
 }
 
+// Per list cell: B = sum over its points of |a_j| max|c|_plane(j), the bound from which the sparse
+// kernel sets its fixed-point scale (every tile of the cell sees a subset of these points).
+__global__ __launch_bounds__(256) void cell_bound_kernel(const wasabi_point *pts, const int32_t *list,
+                                                         const int64_t *off, const DepthDesc *desc,
+                                                         double *bound)
+{
+    __shared__ double red[4];
+    const int64_t p0 = off[blockIdx.x], p1 = off[blockIdx.x + 1];
+    double b = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+        const wasabi_point pt = pts[list[p]];
+        b += (double)fabsf(pt.a) * (double)desc[pt.depth].cmax;
+    }
+    for (int o = 32; o > 0; o >>= 1) b += __shfl_down(b, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) bound[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 __global__ void gather_tile_off_kernel(const int64_t *moff, int64_t ntiles, int nwg, int64_t *off)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -331,6 +350,7 @@ struct TileArgs {
     const wasabi_point *pts;
     const int64_t *tile_off;
     const int32_t *tile_pts;
+    const double *cell_bound;  // per list cell: sum of |a| max|c| over its points
     TileGeom g;
     const float2 *in;  // idwt: Mallat-layout field of the window (contiguous, row stride nx)
     float2 *out;       // MODE_PSI: Mallat field (row stride nx); otherwise pixels (row stride ld)
@@ -483,17 +503,33 @@ __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *ou
 
 // Fixed-point accumulation.  LDS float atomics are slow on this GPU, integer ones are not, so each
 // term a_j * c is formed exactly in FP64 (a product of two FP32 values), rounded once to the grid
-// 2^-s, and added as a 32-bit integer (ds_add_u32).  Integer sums are exact and independent of the
-// order of the adds.  s is chosen per tile from the bound B_t = sum_j |a_j| max|c|_plane(j) over
-// the tile's points (each point adds at most one term to any coefficient): with B_t < 2^e and
-// s = 30 - e, every scaled partial and final sum stays below 2^31 in magnitude.  Rounding uses the
-// FP64 "magic number" 1.5 * 2^52: for |y| < 2^31 the low 32 bits of y + 1.5 * 2^52 are
-// round-to-nearest-even(y) in two's complement.
+// 2^-s, and added as an integer.  Integer sums are exact and independent of the order of the adds.
+// s is chosen per tile from the bound B_t = sum_j |a_j| max|c|_plane(j) over the tile's points
+// (each point adds at most one term to any coefficient): with B_t < 2^e and s = 30 - e, every
+// scaled partial and final sum stays below 2^31 in magnitude.  Rounding uses the FP64 "magic
+// number" 1.5 * 2^52: for |y| < 2^31 the low 32 bits of y + 1.5 * 2^52 are round-to-nearest-even(y)
+// in two's complement.
+// The real and imaginary parts share one 64-bit word, re * 2^32 + im (im sign-extended), added
+// with a single 64-bit atomic: 64-bit modular addition keeps the sum of the words equal to
+// (sum re) * 2^32 + (sum im) exactly, and since |sum im| < 2^31 the low 32 bits give sum im and
+// (word - sum im) / 2^32 gives sum re.
 constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
 
 __device__ inline int to_fixed(float v, double scaled_amp)
 {
     return __double2loint(fma((double)v, scaled_amp, kMagic));
+}
+
+__device__ inline unsigned long long packed_fixed(float2 v, double scaled_amp)
+{
+    const int re = to_fixed(v.x, scaled_amp), im = to_fixed(v.y, scaled_amp);
+    return ((unsigned long long)(unsigned)re << 32) + (unsigned long long)(long long)im;
+}
+
+__device__ inline void unpack_fixed(unsigned long long w, int &re, int &im)
+{
+    im = (int)(unsigned)(w & 0xffffffffull);
+    re = (int)((long long)(w - (unsigned long long)(long long)im) >> 32);
 }
 
 // Adds the kept coefficients of one (tile, point) pair into the tile's LDS accumulators.  Called by
@@ -502,7 +538,7 @@ __device__ inline int to_fixed(float v, double scaled_amp)
 // r) and land at LDS element dst0 + r * ROW + key.  Each row is walked U x 64 entries at a time
 // with all loads issued before the LDS adds.
 template <int L, int VT>
-__device__ inline void add_pair(int *are, int *aim, const void *values, const uint16_t *keys,
+__device__ inline void add_pair(unsigned long long *acc, const void *values, const uint16_t *keys,
                                 int eb, int dst0, int nrows, double scaled_amp, int rstart,
                                 int rcount)
 {
@@ -543,8 +579,7 @@ __device__ inline void add_pair(int *are, int *aim, const void *values, const ui
                 const bool on = c + 64 * u + lane < total;
                 const double sa = on ? scaled_amp : 0.0;
                 const int at = on ? dst0 + drow[u] + key[u] : S::N + lane;
-                atomicAdd(&are[at], to_fixed(v[u].x, sa));
-                atomicAdd(&aim[at], to_fixed(v[u].y, sa));
+                atomicAdd(&acc[at], packed_fixed(v[u], sa));
             }
         }
         (void)nrows;
@@ -573,10 +608,114 @@ __device__ inline void add_pair(int *are, int *aim, const void *values, const ui
                 const int e = c + 64 * u + lane;
                 if (e < rc) {
                     const int at = d + k[u];
-                    atomicAdd(&are[at], to_fixed(v[u].x, scaled_amp));
-                    atomicAdd(&aim[at], to_fixed(v[u].y, scaled_amp));
+                    atomicAdd(&acc[at], packed_fixed(v[u], scaled_amp));
                 }
             }
+        }
+    }
+}
+
+// Walks a batch of (tile, point) pairs (lane k holds pair k's metadata) for L >= 3 (at most 8
+// block rows per pair).  The row ranges of all pairs of the batch are loaded at once, so a pair
+// waits only for its own entries; a pair's rows are walked as one flat range of entries (row r
+// owns [ex_r, ex_r + count_r)), 64 lanes x 2 entries per step, all loads of a step issued before
+// its adds.  Lanes past the end of a range re-read its last entry and add 0 to a word of their own.
+template <int L, int VT>
+struct PairStep {
+    using S = TileShape<L>;
+    int ex[S::TB], off[S::TB];
+    int total, eb, dst0;
+    double sa;
+    float2 v[2];
+    int key[2], drow[2];
+};
+
+template <int L, int VT>
+__device__ inline void pair_setup(PairStep<L, VT> &P, int k, int cnt, const int *m_rs, const int *m_rc,
+                                  int m_eb, int m_dst0, float m_amp, int shift)
+{
+    using S = TileShape<L>;
+    P.total = 0;
+    if (k < cnt) {
+#pragma unroll
+        for (int r = 0; r < S::TB; ++r) {
+            P.ex[r] = P.total;
+            P.off[r] = __builtin_amdgcn_readlane(m_rs[r], k) - P.total;
+            P.total += __builtin_amdgcn_readlane(m_rc[r], k);
+        }
+        P.eb = __builtin_amdgcn_readlane(m_eb, k);
+        P.dst0 = __builtin_amdgcn_readlane(m_dst0, k);
+        P.sa = ldexp((double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k)), shift);
+    } else {
+#pragma unroll
+        for (int r = 0; r < S::TB; ++r) P.ex[r] = P.off[r] = 0;
+        P.eb = 0;
+        P.dst0 = 0;
+        P.sa = 0.0;
+    }
+}
+
+template <int L, int VT>
+__device__ inline void pair_load(PairStep<L, VT> &P, int c, const void *values, const uint16_t *keys)
+{
+    using S = TileShape<L>;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = max(min(c + 64 * u + lane, P.total - 1), 0);
+        int o = P.off[0];
+        P.drow[u] = 0;
+#pragma unroll
+        for (int r = 1; r < S::TB; ++r)
+            if (e >= P.ex[r]) {
+                o = P.off[r];
+                P.drow[u] = r * S::ROW;
+            }
+        const int64_t idx = (int64_t)P.eb + e + o;
+        P.v[u] = load_value<VT>(values, idx);
+        P.key[u] = keys[idx];
+    }
+}
+
+template <int L, int VT>
+__device__ inline void pair_add(unsigned long long *acc, const PairStep<L, VT> &P, int c)
+{
+    using S = TileShape<L>;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const bool on = c + 64 * u + lane < P.total;
+        const int at = on ? P.dst0 + P.drow[u] + P.key[u] : S::N + lane;
+        atomicAdd(&acc[at], packed_fixed(P.v[u], on ? P.sa : 0.0));
+    }
+}
+
+template <int L, int VT>
+__device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, int cnt, int m_nrows,
+                                  int m_bo, int m_nb, int m_bc0, int m_bc1, int m_eb, int m_dst0,
+                                  float m_amp, int shift)
+{
+    using S = TileShape<L>;
+    // all loads issued together: rows past the pair's last re-read its first row, counted as empty
+    int m_rs[S::TB], m_rc[S::TB];
+#pragma unroll
+    for (int r = 0; r < S::TB; ++r) {
+        const int32_t *row = a.blk_off + m_bo + (r < m_nrows ? r : 0) * m_nb;
+        m_rs[r] = row[m_bc0];
+        m_rc[r] = row[m_bc1];
+    }
+#pragma unroll
+    for (int r = 0; r < S::TB; ++r) m_rc[r] = r < m_nrows ? m_rc[r] - m_rs[r] : 0;
+    auto next_pair = [&](int k) {
+        while (k < cnt && __builtin_amdgcn_readlane(m_nrows, k) == 0) ++k;
+        return k;
+    };
+    for (int k = next_pair(0); k < cnt; k = next_pair(k + 1)) {
+        PairStep<L, VT> A;
+        pair_setup(A, k, cnt, m_rs, m_rc, m_eb, m_dst0, m_amp, shift);
+        for (int c = 0; c < A.total; c += 128) {
+            pair_load(A, c, a.values, a.keys);
+            pair_add(acc, A, c);
         }
     }
 }
@@ -586,11 +725,9 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
 {
     using S = TileShape<L>;
     constexpr int NW = kTileThreads / 64;
-    // fixed-point re plane, then im plane, each followed by 64 words that take the (zero) adds of
-    // lanes past the end of a range, one word per lane so that they do not collide
-    __shared__ int acc[2 * (S::N + 64)];
-    __shared__ double red[kTileThreads / 64];
-    int *are = acc, *aim = acc + S::N + 64;
+    // packed fixed-point (re, im) words, followed by 64 words that take the (zero) adds of lanes
+    // past the end of a range, one word per lane so that they do not collide
+    __shared__ unsigned long long acc[S::N + 64];
     const int tile = blockIdx.x;
     const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
@@ -600,18 +737,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
 
-    // bound of every coefficient of this tile -> fixed-point scale 2^shift
-    double bound = 0.0;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTileThreads) {
-        const wasabi_point pt = a.pts[a.tile_pts[p]];
-        bound += (double)fabsf(pt.a) * (double)a.desc[pt.depth].cmax;
-    }
-    for (int o = 32; o > 0; o >>= 1) bound += __shfl_down(bound, o);
-    if (lane == 0) red[wave] = bound;
-    for (int i = threadIdx.x; i < 2 * (S::N + 64); i += kTileThreads) acc[i] = 0;
+    // bound of every coefficient of this tile (its cell's) -> fixed-point scale 2^shift
+    for (int i = threadIdx.x; i < S::N + 64; i += kTileThreads) acc[i] = 0;
+    const double bound = a.cell_bound[lst];
     __syncthreads();
-    bound = 0.0;
-    for (int w = 0; w < NW; ++w) bound += red[w];
     int ex;
     (void)frexp(bound * (1.0 + 1e-6) + 1e-300, &ex);  // bound < 2^ex
     const int shift = min(30 - ex, 1000);
@@ -644,6 +773,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
             }
         }
         const int cnt = (int)min((int64_t)64, (p1 - pb + NW - 1) / NW);
+        if constexpr (S::TB <= 8) {
+            walk_pairs<L, VT>(acc, a, cnt, m_nrows, m_bo, m_nb, m_bc0, m_bc1, m_eb, m_dst0, m_amp, shift);
+            continue;
+        }
         // software pipeline: the row ranges of the next pair load while this pair's entries run
         int k = 0;
         while (k < cnt && __builtin_amdgcn_readlane(m_nrows, k) == 0) ++k;
@@ -669,7 +802,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
                 }
             }
             const float amp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k));
-            add_pair<L, VT>(are, aim, a.values, a.keys, __builtin_amdgcn_readlane(m_eb, k),
+            add_pair<L, VT>(acc, a.values, a.keys, __builtin_amdgcn_readlane(m_eb, k),
                             __builtin_amdgcn_readlane(m_dst0, k), __builtin_amdgcn_readlane(m_nrows, k),
                             ldexp((double)amp, shift), rstart, rcount);
             rstart = nstart;
@@ -679,12 +812,28 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     }
     __syncthreads();
 
-    // fixed point -> FP32 in place (each element converts itself)
+    // fixed point -> FP32 planes (re then im) over the same memory: every thread reads its words
+    // into registers before any thread writes
     const double unscale = ldexp(1.0, -shift);
-    float *sre = (float *)are, *sim = (float *)aim;
-    for (int i = threadIdx.x; i < S::N; i += kTileThreads) {
-        sre[i] = (float)((double)are[i] * unscale);
-        sim[i] = (float)((double)aim[i] * unscale);
+    constexpr int K = (S::N + kTileThreads - 1) / kTileThreads;
+    float fre[K], fim[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * kTileThreads;
+        int re = 0, im = 0;
+        if (i < S::N) unpack_fixed(acc[i], re, im);
+        fre[k] = (float)((double)re * unscale);
+        fim[k] = (float)((double)im * unscale);
+    }
+    __syncthreads();
+    float *sre = (float *)acc, *sim = sre + S::N;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * kTileThreads;
+        if (i < S::N) {
+            sre[i] = fre[k];
+            sim[i] = fim[k];
+        }
     }
     __syncthreads();
 
@@ -993,7 +1142,7 @@ bool use_matrix_path(int64_t n, int64_t ntiles)
 // Plane-sort the points and build the per-tile point lists; results live in `sc`.
 int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,
                Scratch &sc, hipStream_t s, const wasabi_point **sorted_out,
-               int64_t **tile_off_out, int32_t **tile_pts_out, bool *ordered_out)
+               int64_t **tile_off_out, int32_t **tile_pts_out, double **bound_out, bool *ordered_out)
 {
     const int64_t ntiles = (int64_t)g.nlx * g.nly;  // lists
     const int64_t bound = pair_bound(lut, n, g);
@@ -1076,9 +1225,14 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
             CGH_CHECK_LAUNCH("bin_fill_kernel");
         }
     }
+    double *cbound;
+    if ((rc = sc.alloc((void **)&cbound, sizeof(double) * ntiles))) return rc;
+    hipLaunchKernelGGL(cell_bound_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, sorted, list, off, lut->desc, cbound);
+    CGH_CHECK_LAUNCH("cell_bound_kernel");
     *sorted_out = sorted;
     *tile_off_out = off;
     *tile_pts_out = list;
+    *bound_out = cbound;
     return CGH_OK;
 }
 
@@ -1132,6 +1286,7 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.pts = pts;
     a.tile_off = tile_off;
     a.tile_pts = tile_pts;
+    a.cell_bound = nullptr;
     a.g = g;
     a.in = nullptr;
     a.out = out;
@@ -1191,10 +1346,12 @@ int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, in
     int64_t *tile_off;
     int32_t *tile_pts;
     const wasabi_point *sorted;
+    double *cell_bound;
     bool ordered = false;
-    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts, &ordered);
+    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts, &cell_bound, &ordered);
     if (rc) return rc;
     TileArgs a = make_args(lut, sorted, tile_off, tile_pts, g, (float2 *)out, ld);
+    a.cell_bound = cell_bound;
     // Plane pacing (bounded waits; see the dense kernel) when the lists are in plane order and
     // every tile of the grid is resident at once.  CGH_PACE=0 switches it off, CGH_PACE_SLACK sets
     // how many planes a tile may run ahead of the slowest one.
@@ -1258,7 +1415,7 @@ int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_
     const int64_t nbins = (int64_t)lut->prm.n_depth * sort_bands(lut, g) + 1;
     auto r = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
     auto scan = [&](int64_t count) { return r(8 * ((count + 1023) / 1024)); };
-    int64_t t = r(4 * ntiles) + r(8 * (ntiles + 1)) + r(8 * ntiles) + r(4 * pair_bound(lut, n, g)) +
+    int64_t t = r(4 * ntiles) + r(8 * (ntiles + 1)) + r(8 * ntiles) + r(8 * ntiles) + r(4 * pair_bound(lut, n, g)) +
                 r(4 * nbins) + r(8 * (nbins + 1)) + r(8 * nbins) + r(16 * std::max<int64_t>(n, 1)) +
                 scan(nbins);
     if (use_matrix_path(n, ntiles)) {
