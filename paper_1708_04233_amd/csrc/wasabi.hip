@@ -387,6 +387,42 @@ __device__ inline float2 load_value(const void *values, int64_t i)
     return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
 }
 
+// 16-byte loads of stored values: E consecutive complex values (E = 2 for FP32, 4 for FP16/BF16).
+template <int VT>
+struct Wide {
+    static constexpr int E = VT == CGH_F32 ? 2 : 4;
+};
+
+template <int VT>
+__device__ inline float2 unpack_value(uint32_t w)
+{
+    if (VT == CGH_F16) {
+        _Float16 lo, hi;
+        const uint16_t l16 = (uint16_t)(w & 0xffff), h16 = (uint16_t)(w >> 16);
+        __builtin_memcpy(&lo, &l16, 2);
+        __builtin_memcpy(&hi, &h16, 2);
+        return make_float2((float)lo, (float)hi);
+    }
+    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
+// values[i .. i + E) (i a multiple of E) into out[0 .. E)
+template <int VT>
+__device__ inline void load_wide(const void *values, int64_t i, float2 *out)
+{
+    if constexpr (VT == CGH_F32) {
+        const float4 q = *(const float4 *)((const float2 *)values + i);
+        out[0] = make_float2(q.x, q.y);
+        out[1] = make_float2(q.z, q.w);
+    } else {
+        const uint4 q = *(const uint4 *)((const uint32_t *)values + i);
+        out[0] = unpack_value<VT>(q.x);
+        out[1] = unpack_value<VT>(q.y);
+        out[2] = unpack_value<VT>(q.z);
+        out[3] = unpack_value<VT>(q.w);
+    }
+}
+
 // Address of element i of a value array (FP32: float2 elements; FP16/BF16: packed 32-bit pairs).
 template <int VT>
 __device__ inline const void *value_at(const void *values, int64_t i)
@@ -872,11 +908,18 @@ void dense_tile_kernel(TileArgs a)
     const int64_t p0 = a.tile_off[lst], p1 = a.tile_off[lst + 1];
     const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
 
-    // the lane's coefficient i: c = 512 w + 64 i + lane -> tile block b = c / BB (block row b / TB,
-    // column b % TB), code c % BB.  Recomputed where needed rather than held in registers.
-    auto tbr_of = [&](int i) { return ((wave * 512 + i * 64 + lane) / BB) / S::TB; };
-    auto tbc_of = [&](int i) { return ((wave * 512 + i * 64 + lane) / BB) % S::TB; };
-    auto code_of = [&](int i) { return (wave * 512 + i * 64 + lane) % BB; };
+    // The lane's coefficient i (of PER = 8), as an index c in the tile's block-major order: tile
+    // block b = c / BB (block row b / TB, column b % TB), code c % BB.  For L >= 3 a lane holds
+    // coefficient i = k E + e as 512 w + 64 E k + E lane + e, so that one 16-byte load per k
+    // fetches the lane's E consecutive codes; for L < 3, c = 512 w + 64 i + lane.  Recomputed where
+    // needed rather than held in registers.
+    constexpr int E = BB >= 64 ? Wide<VT>::E : 1;
+    auto coef_of = [&](int i) {
+        return BB >= 64 ? wave * 512 + 64 * E * (i / E) + E * lane + i % E : wave * 512 + i * 64 + lane;
+    };
+    auto tbr_of = [&](int i) { return (coef_of(i) / BB) / S::TB; };
+    auto tbc_of = [&](int i) { return (coef_of(i) / BB) % S::TB; };
+    auto code_of = [&](int i) { return coef_of(i) % BB; };
     float are[PER], aim[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) are[i] = aim[i] = 0.0f;
@@ -911,6 +954,9 @@ void dense_tile_kernel(TileArgs a)
                     }
                 }
                 const int cnt = (int)min((int64_t)64, q1 - pb);
+                // one 16-byte load per E coefficients of a lane; a block the pair does not cover
+                // reads the zero values instead, so the loads and FMAs need no branches
+                const int wofs = (wave * 512) % (BB * S::TB);  // the wave's first coefficient in its row
                 for (int k = 0; k < cnt; ++k) {
                     const int clo = __builtin_amdgcn_readlane(m_clo, k), chi = __builtin_amdgcn_readlane(m_chi, k);
                     if (chi <= clo) continue;
@@ -918,14 +964,17 @@ void dense_tile_kernel(TileArgs a)
                     const float amp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k));
                     float2 v[PER];
 #pragma unroll
-                    for (int i = 0; i < PER; ++i)
-                        if (tbc_of(i) >= clo && tbc_of(i) < chi) v[i] = load_value<VT>(a.dense, b0 + (int64_t)tbc_of(i) * BB + code_of(i));
+                    for (int j = 0; j < PER / E; ++j) {
+                        const int tc = tbc_of(j * E);
+                        const int64_t rel = 64 * E * j + E * lane;
+                        const int64_t at = (tc >= clo && tc < chi) ? b0 + wofs + rel : a.dense_zero + rel;
+                        load_wide<VT>(a.dense, at, v + j * E);
+                    }
 #pragma unroll
-                    for (int i = 0; i < PER; ++i)
-                        if (tbc_of(i) >= clo && tbc_of(i) < chi) {
-                            are[i] = fmaf(amp, v[i].x, are[i]);
-                            aim[i] = fmaf(amp, v[i].y, aim[i]);
-                        }
+                    for (int i = 0; i < PER; ++i) {
+                        are[i] = fmaf(amp, v[i].x, are[i]);
+                        aim[i] = fmaf(amp, v[i].y, aim[i]);
+                    }
                 }
             }
         };
