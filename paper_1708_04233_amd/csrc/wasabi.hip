@@ -40,6 +40,22 @@ struct TileGeom {
     int32_t nlx, nly;  // list cells per row / column
 };
 
+// Tile handled by workgroup b: tiles go out in blocks of 32 x 32 tiles (block rows top to bottom,
+// blocks left to right, tiles row-major inside a block; edge blocks are smaller), so the tiles that
+// are resident together cover a compact region and share points, depth planes and table data.
+__device__ inline void tile_of(int b, const TileGeom &g, int &ty, int &tx)
+{
+    constexpr int T = 32;
+    const int R = b / (T * g.ntx);                    // block row
+    const int r = b - R * T * g.ntx;
+    const int h = min(T, g.nty - T * R);              // its height in tiles
+    const int C = r / (h * T);                        // block column
+    const int w_off = r - C * h * T;
+    const int w = min(T, g.ntx - T * C);              // its width in tiles
+    ty = T * R + w_off / w;
+    tx = T * C + w_off % w;
+}
+
 // List cells touched by the occupied part of point p's table; false if none.
 __device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, int n_depth, int L,
                                  const TileGeom &g, int &ty0, int &ty1, int &tx0, int &tx1)
@@ -765,7 +781,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     // past the end of a range, one word per lane so that they do not collide
     __shared__ unsigned long long acc[S::N + 64];
     const int tile = blockIdx.x;
-    const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
+    int ty, tx;
+    tile_of(tile, a.g, ty, tx);
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int tbh = th >> L, tbw = tw >> L;
     const int sup = a.g.cell / kT, lst = (ty / sup) * a.g.nlx + tx / sup;  // the tile's list cell
@@ -900,7 +917,8 @@ void dense_tile_kernel(TileArgs a)
     constexpr int PER = kT * kT / kDenseThreads;  // coefficients per lane (8)
     __shared__ float sbuf[2 * S::N];
     const int tile = blockIdx.x;
-    const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
+    int ty, tx;
+    tile_of(tile, a.g, ty, tx);
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1097,7 +1115,8 @@ __global__ __launch_bounds__(kThreads) void idwt_kernel(TileArgs a)
     __shared__ float sre[S::N];
     __shared__ float sim[S::N];
     const int tile = blockIdx.x;
-    const int ty = tile / a.g.ntx, tx = tile - ty * a.g.ntx;
+    int ty, tx;
+    tile_of(tile, a.g, ty, tx);
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     tile_mallat_io<L, true, kThreads>(sre, sim, const_cast<float2 *>(a.in), a.g, ty, tx, th, tw);
     __syncthreads();
