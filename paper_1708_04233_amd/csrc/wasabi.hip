@@ -446,6 +446,56 @@ __device__ inline const void *value_at(const void *values, int64_t i)
     return (const char *)values + i * (VT == CGH_F32 ? 8 : 4);
 }
 
+// Loads the tile's coefficients from the window's Mallat field (rows of nx) into the tile buffer.
+// The level / band loops are unrolled, so every slot of the register staging arrays is known at
+// compile time, and every load of a thread is issued before any of its stores to LDS.
+template <int L, int NT>
+__device__ inline void tile_mallat_load(float *sre, float *sim, const float2 *field, const TileGeom &g,
+                                        int ty, int tx, int th, int tw)
+{
+    using S = TileShape<L>;
+    constexpr int K = 3 * ((kT * kT / 4 + NT - 1) / NT) * L + (kT * kT / (1 << (2 * L)) + NT - 1) / NT;
+    float2 v[K];
+    int at[K];
+    int slot = 0;
+#pragma unroll
+    for (int l = 1; l <= L; ++l) {
+        const int wf = kT >> l, h = S::B >> l;
+#pragma unroll
+        for (int band = 1; band <= 3; ++band) {
+            const int64_t row0 = (band & 2) ? (g.ny >> l) : 0, col0 = (band & 1) ? (g.nx >> l) : 0;
+#pragma unroll
+            for (int i0 = 0; i0 < wf * wf; i0 += NT, ++slot) {
+                const int i = i0 + threadIdx.x, m = i / wf, n = i % wf;
+                at[slot] = -1;
+                if (i < wf * wf && m < (th >> l) && n < (tw >> l)) {
+                    const int code = (((band & 2) ? h : 0) + (m & (h - 1))) * S::B + ((band & 1) ? h : 0) + (n & (h - 1));
+                    at[slot] = (m / h) * S::ROW + (n / h) * S::BS + code;
+                    v[slot] = field[(row0 + (int64_t)ty * wf + m) * g.nx + col0 + (int64_t)tx * wf + n];
+                }
+            }
+        }
+    }
+    {
+        constexpr int wf = kT >> L;
+#pragma unroll
+        for (int i0 = 0; i0 < wf * wf; i0 += NT, ++slot) {
+            const int i = i0 + threadIdx.x, m = i / wf, n = i % wf;
+            at[slot] = -1;
+            if (i < wf * wf && m < (th >> L) && n < (tw >> L)) {
+                at[slot] = m * S::ROW + n * S::BS;
+                v[slot] = field[((int64_t)ty * wf + m) * g.nx + (int64_t)tx * wf + n];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k < slot && at[k] >= 0) {
+            sre[at[k]] = v[k].x;
+            sim[at[k]] = v[k].y;
+        }
+}
+
 // Moves the tile's coefficients between LDS and the window's Mallat layout (rows of nx).
 template <int L, bool TO_LDS, int NT>
 __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, const TileGeom &g,
@@ -1118,7 +1168,7 @@ __global__ __launch_bounds__(kThreads) void idwt_kernel(TileArgs a)
     int ty, tx;
     tile_of(tile, a.g, ty, tx);
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
-    tile_mallat_io<L, true, kThreads>(sre, sim, const_cast<float2 *>(a.in), a.g, ty, tx, th, tw);
+    tile_mallat_load<L, kThreads>(sre, sim, a.in, a.g, ty, tx, th, tw);
     __syncthreads();
     tile_inverse_and_store<L, kThreads>(sre, sim, a.out, a.ld, ty, tx, th, tw);
 }
