@@ -91,15 +91,17 @@ constexpr double kDenseGamma = 0.35;
 // On-chip tile buffer layout: block (r, c) of a tile starts at r * row_stride + c * block_stride.
 // The pads decide how the LDS banks of equal in-block codes of neighbouring blocks and block rows
 // line up; these values minimise the bank conflicts of the superposition's scattered atomic adds
-// (a model of the 64-lane adds over the kept entries of real tables, for 32 and 64 banks).
+// (a model of the 64-lane adds over the kept entries of real tables, for 32 and 64 banks).  L = 4
+// has none: its unpadded 64 x 64 tile of 8-byte words is exactly 32 KiB, so five tiles share a
+// compute unit's 160 KiB instead of four, which measured faster than the pads' fewer conflicts.
 __host__ __device__ constexpr int block_stride(int L)
 {
-    return L <= 2 ? (1 << (2 * L)) + (1 << L) : (1 << (2 * L)) + (1 << (L - 2));
+    return L <= 2 ? (1 << (2 * L)) + (1 << L) : (L == 4 ? 256 : (1 << (2 * L)) + (1 << (L - 2)));
 }
 
 __host__ __device__ constexpr int row_pad(int L)
 {
-    return L == 3 ? 32 : (L == 4 ? 8 : 0);
+    return L == 3 ? 32 : 0;
 }
 
 struct DepthDesc {

@@ -38,6 +38,8 @@ struct TileGeom {
     int32_t ntx, nty;  // tiles per row / column
     int32_t cell;      // point lists are kept per cell of cell x cell pixels (a square of tiles)
     int32_t nlx, nly;  // list cells per row / column
+    int32_t ltx0, lty0;  // the window's first tile on the tile grid of the lists (0 unless the
+                         // lists were built for a larger window holding this one)
 };
 
 // Tile handled by workgroup b: tiles go out in blocks of 32 x 32 tiles (block rows top to bottom,
@@ -680,7 +682,7 @@ __device__ inline void add_pair(unsigned long long *acc, const void *values, con
             for (int u = 0; u < 2; ++u) {
                 const bool on = c + 64 * u + lane < total;
                 const double sa = on ? scaled_amp : 0.0;
-                const int at = on ? dst0 + drow[u] + key[u] : S::N + lane;
+                const int at = on ? dst0 + drow[u] + key[u] : lane;
                 atomicAdd(&acc[at], packed_fixed(v[u], sa));
             }
         }
@@ -787,7 +789,7 @@ __device__ inline void pair_add(unsigned long long *acc, const PairStep<L, VT> &
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const bool on = c + 64 * u + lane < P.total;
-        const int at = on ? P.dst0 + P.drow[u] + P.key[u] : S::N + lane;
+        const int at = on ? P.dst0 + P.drow[u] + P.key[u] : lane;
         atomicAdd(&acc[at], packed_fixed(P.v[u], on ? P.sa : 0.0));
     }
 }
@@ -822,26 +824,152 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
     }
 }
 
+// One fixed-point word of the tile as FP32 (re, im).
+__device__ inline float2 fixed_value(unsigned long long w, double unscale)
+{
+    int re, im;
+    unpack_fixed(w, re, im);
+    return make_float2((float)((double)re * unscale), (float)((double)im * unscale));
+}
+
+// One 2D inverse Haar step for one output of a quadruple: the output at row parity a, column parity
+// b of the next finer level.  Same operations, in the same order, as the in-LDS inverse.
+__device__ inline float2 haar_up(float2 s, float2 h, float2 v, float2 d, int a, int b)
+{
+    const float hr = b ? -h.x : h.x, hi = b ? -h.y : h.y;
+    const float vr = a ? -v.x : v.x, vi = a ? -v.y : v.y;
+    const float dr = (a ^ b) ? -d.x : d.x, di = (a ^ b) ? -d.y : d.y;
+    return make_float2((s.x + hr + vr + dr) * 0.5f, (s.y + hi + vi + di) * 0.5f);
+}
+
+// Inverse Haar of the tile from its fixed-point words.  The coarse quarter of every block (levels
+// >= 2 and the scaling band, its top-left B/2 x B/2 corner) is turned into FP32 (re, im) in place
+// and inverted in LDS down to level 1; the finest level, three quarters of the coefficients, goes
+// from the fixed-point words through registers straight to the pixels: a thread takes one level-1
+// position, i.e. a 2 x 2 pixel quad, and the threads of a wave take consecutive quads of a row, so
+// each store instruction writes whole rows of the tile.
+template <int L, int NT>
+__device__ inline void fixed_inverse_store(unsigned long long *acc, double unscale, float2 *out,
+                                           int64_t ld, int ty, int tx, int th, int tw)
+{
+    using S = TileShape<L>;
+    constexpr int B = S::B, H1 = B / 2, QT = kT / 2;   // level-1 band extent in a block / tile
+    float2 *f = reinterpret_cast<float2 *>(acc);
+    auto word = [](int blk, int m, int n) { return (blk / S::TB) * S::ROW + (blk % S::TB) * S::BS + m * B + n; };
+    for (int i = threadIdx.x; i < QT * QT; i += NT) {
+        const int at = word(i / (H1 * H1), (i % (H1 * H1)) / H1, i % H1);
+        f[at] = fixed_value(acc[at], unscale);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = L; l >= 2; --l) {
+        const int h = B >> l, per = h * h, nq = (kT >> l) * (kT >> l);
+        constexpr int MAXQ = ((kT / 4) * (kT / 4) + NT - 1) / NT;
+        float2 q[MAXQ][4];
+        int at0[MAXQ];
+#pragma unroll
+        for (int k = 0; k < MAXQ; ++k) {
+            const int qi = threadIdx.x + NT * k;
+            if (qi < nq) {
+                const int blk = qi / per, m = (qi % per) / h, n = qi % h;
+                const int s0 = word(blk, m, n);
+                at0[k] = word(blk, 2 * m, 2 * n);
+                q[k][0] = f[s0];
+                q[k][1] = f[s0 + h];
+                q[k][2] = f[s0 + h * B];
+                q[k][3] = f[s0 + h * B + h];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXQ; ++k) {
+            const int qi = threadIdx.x + NT * k;
+            if (qi < nq) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) f[at0[k] + i * B + j] = haar_up(q[k][0], q[k][1], q[k][2], q[k][3], i, j);
+            }
+        }
+        __syncthreads();
+    }
+    const bool wide = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)ld * sizeof(float2)) & 15) == 0;
+    for (int qi = threadIdx.x; qi < QT * QT; qi += NT) {
+        const int qm = qi / QT, qn = qi % QT;           // quad row / column in the tile
+        const int br = qm / H1, bc = qn / H1, m = qm % H1, n = qn % H1;
+        if (br >= (th >> L) || bc >= (tw >> L)) continue;
+        const int blk = br * S::TB + bc;
+        const float2 S1 = f[word(blk, m, n)];
+        const float2 H = fixed_value(acc[word(blk, m, H1 + n)], unscale);
+        const float2 V = fixed_value(acc[word(blk, H1 + m, n)], unscale);
+        const float2 D = fixed_value(acc[word(blk, H1 + m, H1 + n)], unscale);
+        float2 *o = out + ((int64_t)ty * kT + 2 * qm) * ld + (int64_t)tx * kT + 2 * qn;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float2 p0 = haar_up(S1, H, V, D, i, 0), p1 = haar_up(S1, H, V, D, i, 1);
+            if (wide) {
+                *reinterpret_cast<float4 *>(o + i * ld) = make_float4(p0.x, p0.y, p1.x, p1.y);
+            } else {
+                o[i * ld] = p0;
+                o[i * ld + 1] = p1;
+            }
+        }
+    }
+}
+
+// The tile's coefficients from its fixed-point words straight into the window's Mallat layout.
+template <int L, int NT>
+__device__ inline void fixed_mallat_store(const unsigned long long *acc, double unscale, float2 *field,
+                                          const TileGeom &g, int ty, int tx, int th, int tw)
+{
+    using S = TileShape<L>;
+    const int64_t nx = g.nx;
+#pragma unroll
+    for (int l = 1; l <= L; ++l) {
+        const int wf = kT >> l, h = S::B >> l;
+        const int hb = th >> l, wb = tw >> l;
+#pragma unroll
+        for (int band = 1; band <= 3; ++band) {
+            const int64_t row0 = (band & 2) ? (g.ny >> l) : 0, col0 = (band & 1) ? (g.nx >> l) : 0;
+            for (int i = threadIdx.x; i < wf * wf; i += NT) {
+                const int m = i / wf, n = i % wf;
+                if (m >= hb || n >= wb) continue;
+                const int code = (((band & 2) ? h : 0) + (m & (h - 1))) * S::B + ((band & 1) ? h : 0) + (n & (h - 1));
+                field[(row0 + (int64_t)ty * wf + m) * nx + col0 + (int64_t)tx * wf + n] =
+                    fixed_value(acc[(m / h) * S::ROW + (n / h) * S::BS + code], unscale);
+            }
+        }
+    }
+    constexpr int wf = kT >> L;
+    const int hb = th >> L, wb = tw >> L;
+    for (int i = threadIdx.x; i < wf * wf; i += NT) {
+        const int m = i / wf, n = i % wf;
+        if (m >= hb || n >= wb) continue;
+        field[((int64_t)ty * wf + m) * nx + (int64_t)tx * wf + n] = fixed_value(acc[m * S::ROW + n * S::BS], unscale);
+    }
+}
+
 template <int L, int VT, int MODE>
 __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
 {
     using S = TileShape<L>;
     constexpr int NW = kTileThreads / 64;
-    // packed fixed-point (re, im) words, followed by 64 words that take the (zero) adds of lanes
-    // past the end of a range, one word per lane so that they do not collide
-    __shared__ unsigned long long acc[S::N + 64];
+    // packed fixed-point (re, im) words; lanes past the end of a range add zero to word `lane`,
+    // one word per lane so that they do not collide
+    __shared__ unsigned long long acc[S::N];
     const int tile = blockIdx.x;
     int ty, tx;
     tile_of(tile, a.g, ty, tx);
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int tbh = th >> L, tbw = tw >> L;
-    const int sup = a.g.cell / kT, lst = (ty / sup) * a.g.nlx + tx / sup;  // the tile's list cell
+    const int sup = a.g.cell / kT;  // the tile's list cell:
+    const int lst = ((ty + a.g.lty0) / sup) * a.g.nlx + (tx + a.g.ltx0) / sup;
     const int64_t p0 = a.tile_off[lst], p1 = a.tile_off[lst + 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
 
     // bound of every coefficient of this tile (its cell's) -> fixed-point scale 2^shift
-    for (int i = threadIdx.x; i < S::N + 64; i += kTileThreads) acc[i] = 0;
+    for (int i = threadIdx.x; i < S::N; i += kTileThreads) acc[i] = 0;
     const double bound = a.cell_bound[lst];
     __syncthreads();
     int ex;
@@ -915,36 +1043,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     }
     __syncthreads();
 
-    // fixed point -> FP32 planes (re then im) over the same memory: every thread reads its words
-    // into registers before any thread writes
     const double unscale = ldexp(1.0, -shift);
-    constexpr int K = (S::N + kTileThreads - 1) / kTileThreads;
-    float fre[K], fim[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int i = threadIdx.x + k * kTileThreads;
-        int re = 0, im = 0;
-        if (i < S::N) unpack_fixed(acc[i], re, im);
-        fre[k] = (float)((double)re * unscale);
-        fim[k] = (float)((double)im * unscale);
-    }
-    __syncthreads();
-    float *sre = (float *)acc, *sim = sre + S::N;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int i = threadIdx.x + k * kTileThreads;
-        if (i < S::N) {
-            sre[i] = fre[k];
-            sim[i] = fim[k];
-        }
-    }
-    __syncthreads();
-
-    if (MODE == MODE_PSI) {
-        tile_mallat_io<L, false, kTileThreads>(sre, sim, a.out, a.g, ty, tx, th, tw);
-    } else {
-        tile_inverse_and_store<L, kTileThreads>(sre, sim, a.out, a.ld, ty, tx, th, tw);
-    }
+    if constexpr (MODE == MODE_PSI)
+        fixed_mallat_store<L, kTileThreads>(acc, unscale, a.out, a.g, ty, tx, th, tw);
+    else
+        fixed_inverse_store<L, kTileThreads>(acc, unscale, a.out, a.ld, ty, tx, th, tw);
 }
 
 // Dense-layout superposition.  Wave w of the tile's 8 waves owns the 512 coefficients
@@ -972,7 +1075,8 @@ void dense_tile_kernel(TileArgs a)
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int sup = a.g.cell / kT, lst = (ty / sup) * a.g.nlx + tx / sup;  // the tile's list cell
+    const int sup = a.g.cell / kT;  // the tile's list cell:
+    const int lst = ((ty + a.g.lty0) / sup) * a.g.nlx + (tx + a.g.ltx0) / sup;
     const int64_t p0 = a.tile_off[lst], p1 = a.tile_off[lst + 1];
     const int64_t gy0 = a.g.oy + (int64_t)ty * kT, gx0 = a.g.ox + (int64_t)tx * kT;
 
@@ -1186,6 +1290,7 @@ TileGeom make_geom(int64_t ox, int64_t oy, int32_t nx, int32_t ny)
     g.cell = kT;
     g.nlx = g.ntx;
     g.nly = g.nty;
+    g.ltx0 = g.lty0 = 0;
     return g;
 }
 
@@ -1451,31 +1556,45 @@ int64_t resident_capacity(int L, int vt, int mode)
     return c;
 }
 
-int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox,
-                   int64_t oy, int32_t nx, int32_t ny, void *out, int64_t ld, int mode,
-                   hipStream_t s, bool allow_pace = true, Scratch *ext = nullptr)
-{
-    int rc = prepare_pool();
-    if (rc) return rc;
-    TileGeom g = make_geom(ox, oy, nx, ny);
-    choose_lists(g);
-    Scratch local(s);
-    Scratch &sc = ext ? *ext : local;
+// Points binned for a window: the plane-sorted points, the per-cell point lists and bounds.
+struct Binned {
+    TileGeom g;
+    const wasabi_point *sorted;
     int64_t *tile_off;
     int32_t *tile_pts;
-    const wasabi_point *sorted;
     double *cell_bound;
-    bool ordered = false;
-    rc = bin_points(lut, pts, n, g, sc, s, &sorted, &tile_off, &tile_pts, &cell_bound, &ordered);
-    if (rc) return rc;
-    TileArgs a = make_args(lut, sorted, tile_off, tile_pts, g, (float2 *)out, ld);
-    a.cell_bound = cell_bound;
+    bool ordered;
+};
+
+int bin_window(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox, int64_t oy,
+               int32_t nx, int32_t ny, Scratch &sc, hipStream_t s, Binned &b)
+{
+    b.g = make_geom(ox, oy, nx, ny);
+    choose_lists(b.g);
+    b.ordered = false;
+    return bin_points(lut, pts, n, b.g, sc, s, &b.sorted, &b.tile_off, &b.tile_pts, &b.cell_bound, &b.ordered);
+}
+
+// Superposition of the window (ox, oy, nx, ny) from the lists of `b`, whose window holds this one
+// with this one's origin on its tile grid.
+int launch_window(const wasabi_lut *lut, const Binned &b, int64_t ox, int64_t oy, int32_t nx, int32_t ny,
+                  void *out, int64_t ld, int mode, hipStream_t s, bool allow_pace, Scratch &sc)
+{
+    TileGeom g = make_geom(ox, oy, nx, ny);
+    g.cell = b.g.cell;
+    g.nlx = b.g.nlx;
+    g.nly = b.g.nly;
+    g.ltx0 = (int32_t)((ox - b.g.ox) / kT);
+    g.lty0 = (int32_t)((oy - b.g.oy) / kT);
+    TileArgs a = make_args(lut, b.sorted, b.tile_off, b.tile_pts, g, (float2 *)out, ld);
+    a.cell_bound = b.cell_bound;
     // Plane pacing (bounded waits; see the dense kernel) when the lists are in plane order and
     // every tile of the grid is resident at once.  CGH_PACE=0 switches it off, CGH_PACE_SLACK sets
     // how many planes a tile may run ahead of the slowest one.
     static const int pace_env = getenv("CGH_PACE") ? atoi(getenv("CGH_PACE")) : 1;
     static const int slack_env = getenv("CGH_PACE_SLACK") ? atoi(getenv("CGH_PACE_SLACK")) : 5;
-    if (allow_pace && pace_env && lut->dense && ordered && lut->L >= 3 && lut->prm.n_depth <= kPaceMaxPlanes &&
+    int rc;
+    if (allow_pace && pace_env && lut->dense && b.ordered && lut->L >= 3 && lut->prm.n_depth <= kPaceMaxPlanes &&
         resident_capacity(lut->L, lut->prm.value_dtype, mode) >= (int64_t)g.ntx * g.nty) {
         int *done;
         const size_t bytes = sizeof(int) * (size_t)lut->prm.n_depth * kPaceCounters;
@@ -1486,6 +1605,19 @@ int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, in
     }
     if (mode == MODE_PSI) return launch_tile<MODE_PSI>(lut->L, lut->prm.value_dtype, a, s);
     return launch_tile<MODE_FUSED>(lut->L, lut->prm.value_dtype, a, s);
+}
+
+int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox,
+                   int64_t oy, int32_t nx, int32_t ny, void *out, int64_t ld, int mode,
+                   hipStream_t s, bool allow_pace = true, Scratch *ext = nullptr)
+{
+    int rc = prepare_pool();
+    if (rc) return rc;
+    Scratch local(s);
+    Scratch &sc = ext ? *ext : local;
+    Binned b;
+    if ((rc = bin_window(lut, pts, n, ox, oy, nx, ny, sc, s, b))) return rc;
+    return launch_window(lut, b, ox, oy, nx, ny, out, ld, mode, s, allow_pace, sc);
 }
 
 int check_common(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox, int64_t oy,
@@ -1596,13 +1728,21 @@ extern "C" int wasabi_hologram(const wasabi_lut *lut, const wasabi_point *pts, i
     Scratch sc(s);
     float2 *psi;
     if ((rc = sc.alloc((void **)&psi, sizeof(float2) * (size_t)sx * sy))) return rc;
+    // The points are binned once for the whole window when every sub-hologram starts on its tile
+    // grid; otherwise per sub-hologram.
+    const bool once = (sub % kT == 0) || (sx == nx && sy == ny);
+    Binned b;
+    if (once && (rc = bin_window(lut, pts, n, ox, oy, nx, ny, sc, s, b))) return rc;
     // Sec. 2, large-scale procedure: for every sub-hologram (s, t), shift the points
     // (x'_j = x_j - s N_h), superpose in the wavelet domain, invert into the hologram.
     for (int64_t t0 = 0; t0 < ny; t0 += sub) {
         for (int64_t s0 = 0; s0 < nx; s0 += sub) {
             const int32_t wx = (int32_t)std::min<int64_t>(sub, nx - s0);
             const int32_t wy = (int32_t)std::min<int64_t>(sub, ny - t0);
-            rc = superpose_impl(lut, pts, n, ox + s0, oy + t0, wx, wy, psi, wx, MODE_PSI, s);
+            if (once)
+                rc = launch_window(lut, b, ox + s0, oy + t0, wx, wy, psi, wx, MODE_PSI, s, true, sc);
+            else
+                rc = superpose_impl(lut, pts, n, ox + s0, oy + t0, wx, wy, psi, wx, MODE_PSI, s);
             if (rc) return rc;
             float2 *uw = (float2 *)u + t0 * ld_u + s0;
             rc = idwt_impl(psi, wx, wy, lut->L, uw, ld_u, s);

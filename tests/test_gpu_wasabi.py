@@ -88,7 +88,8 @@ def test_idwt_matches_oracle(orc, levels):
 
 
 @pytest.mark.parametrize("levels,sub,gamma", [(3, 64, 0.25), (3, 0, 0.25), (4, 96, 0.25),
-                                              (2, 40, 0.25), (3, 64, 0.84), (4, 96, 0.6)])
+                                              (2, 40, 0.25), (3, 64, 0.84), (4, 96, 0.6),
+                                              (1, 0, 0.25), (5, 0, 0.25), (6, 0, 0.25)])
 def test_hologram_and_fused_match_oracle(orc, levels, sub, gamma):
     ref, gpu = _luts(orc, levels, gamma)
     B = 1 << levels
@@ -103,6 +104,15 @@ def test_hologram_and_fused_match_oracle(orc, levels, sub, gamma):
     assert np.all(got[:, nx:] == 5.0)
     fused = cgh.wasabi_hologram_fused(gpu, q, X0, Y0, nx, ny).cpu().numpy()
     assert _rel(fused, want) < TOL
+    # into a view whose rows are not 16-byte aligned (odd row stride, 8-byte offset)
+    big = torch.full((ny, nx + 9), 7.0, dtype=torch.complex64, device="cuda")
+    view = big[:, 1:1 + nx]
+    cgh.wasabi_hologram_fused(gpu, q, X0, Y0, nx, ny, u=view)
+    got = big.cpu().numpy()
+    assert _rel(got[:, 1:1 + nx], want) < TOL
+    if gamma < 0.35:               # fixed-point sums: bitwise the same as the aligned output
+        assert np.array_equal(got[:, 1:1 + nx], fused)
+    assert np.all(got[:, 0] == 7.0) and np.all(got[:, 1 + nx:] == 7.0)
 
 
 def test_no_points_and_invalid_points(orc):
