@@ -10,7 +10,8 @@ Paper: Shimobaba et al., "Fast, large-scale hologram calculation in wavelet doma
   * ``psf_table``       -- Sec. 2 step 1 (u_z = exp(ikr) circ(.)).
   * ``haar_forward`` / ``haar_inverse`` -- Sec. 2 steps 1 and 3, Fig. 2(a) layout (Haar wavelet).
   * ``build_lut``       -- Sec. 2 step 1 (transform + keep the N_r strongest coefficients).
-  * ``quantize``        -- depth discretisation and the 2^L grid that Eq.(2) needs.
+  * ``quantize``        -- depth discretisation and the 2^L grid that Eq.(2) needs (or, with
+                           phase tables, the pixel grid and the table of the point's phase).
   * ``superpose``       -- Eq.(2) with the sub-hologram shift of the large-scale procedure.
   * ``wasabi``          -- superpose followed by the inverse transform (Sec. 2 steps 2-4).
 """
@@ -52,9 +53,9 @@ def _load():
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.oracle_direct.argtypes = [P, I64, I32, I32, I64, I64, D, D, I32, P]
     lib.oracle_direct.restype = None
-    lib.oracle_lut_geometry.argtypes = [D, D, D, D, I32, I32, I32, D, P, P, P, P]
+    lib.oracle_lut_geometry.argtypes = [D, D, D, D, I32, I32, I32, D, I32, P, P, P, P]
     lib.oracle_lut_geometry.restype = ctypes.c_int
-    lib.oracle_psf_table.argtypes = [D, D, I32, D, D, P]
+    lib.oracle_psf_table.argtypes = [D, D, I32, I32, I32, D, D, P]
     lib.oracle_psf_table.restype = None
     lib.oracle_haar_forward.argtypes = [P, I32, I32, I32]
     lib.oracle_haar_forward.restype = None
@@ -64,9 +65,9 @@ def _load():
     lib.oracle_select.restype = None
     lib.oracle_round_value.argtypes = [D, I32]
     lib.oracle_round_value.restype = D
-    lib.oracle_build_lut.argtypes = [D, D, I32, I32, P, P, P, P, P, I32, P, P]
+    lib.oracle_build_lut.argtypes = [D, D, I32, I32, P, P, P, P, P, P, P, I32, P, P]
     lib.oracle_build_lut.restype = None
-    lib.oracle_quantize.argtypes = [P, I64, D, D, D, I32, I32, P, P, P, P]
+    lib.oracle_quantize.argtypes = [P, I64, D, D, D, I32, I32, I32, P, P, P, P]
     lib.oracle_quantize.restype = None
     lib.oracle_superpose.argtypes = [I32, P, P, P, P, P, P, P, P, I64, I64, I64, I32, I32, P]
     lib.oracle_superpose.restype = None
@@ -112,37 +113,54 @@ class LutParams:
     max_window: int = 1024
     gamma: float = 0.05
     value_dtype: int = F32
+    phases: int = 0        # 1: one table per depth and position inside the 2^L block (4^L per depth)
 
 
 @dataclass
 class Lut:
-    """Canonical LUT: plane d owns entries [off[d], off[d+1]) sorted by flat table index."""
+    """Canonical LUT: table t owns entries [off[t], off[t+1]) sorted by flat table index.
+
+    Without phase tables table t is plane t.  With them table t = d 4^L + sy 2^L + sx holds plane
+    d's PSF for a point sx columns right of and sy rows below its 2^L block's corner."""
     params: LutParams
-    z: np.ndarray      # (n_depth,) plane depth z_d, metres
-    R: np.ndarray      # (n_depth,) PSF radius, pixels
-    W: np.ndarray      # (n_depth,) table side, int32
-    Nr: np.ndarray     # (n_depth,) kept coefficients, int64
-    off: np.ndarray    # (n_depth + 1,) int64
+    z: np.ndarray      # (n_tables,) plane depth z_d, metres
+    R: np.ndarray      # (n_tables,) PSF radius, pixels
+    W: np.ndarray      # (n_tables,) table side, int32
+    Nr: np.ndarray     # (n_tables,) kept coefficients, int64
+    off: np.ndarray    # (n_tables + 1,) int64
     idx: np.ndarray    # (sum Nr,) int32 flat index row * W + col
     val: np.ndarray    # (sum Nr,) complex128, already rounded to the storage dtype
+    sx: np.ndarray = None  # (n_tables,) disk centre shift from the table centre, columns
+    sy: np.ndarray = None  # (n_tables,) rows
+
+
+def n_phases(prm: LutParams) -> int:
+    return 1 << (2 * prm.levels) if prm.phases else 1
 
 
 def lut_geometry(prm: LutParams):
+    """Per table: z, R, W, N_r (planes repeated once per phase with phase tables), and the disk
+    centre shifts sx, sy."""
     lib = _load()
     n = prm.n_depth
     z = np.zeros(n); R = np.zeros(n)
     W = np.zeros(n, dtype=np.int32); Nr = np.zeros(n, dtype=np.int64)
     rc = lib.oracle_lut_geometry(prm.wavelength, prm.pitch, prm.z_min, prm.z_max, n, prm.levels,
-                                 prm.max_window, prm.gamma, _p(z), _p(R), _p(W), _p(Nr))
+                                 prm.max_window, prm.gamma, int(prm.phases), _p(z), _p(R), _p(W), _p(Nr))
     if rc != 0:
         raise ValueError("a PSF table exceeds max_window")
-    return z, R, W, Nr
+    P, B = n_phases(prm), 1 << prm.levels
+    ph = np.tile(np.arange(P, dtype=np.int32), n)
+    sx = (ph % B if prm.phases else np.zeros_like(ph)).astype(np.int32)
+    sy = (ph // B if prm.phases else np.zeros_like(ph)).astype(np.int32)
+    return np.repeat(z, P), np.repeat(R, P), np.repeat(W, P), np.repeat(Nr, P), sx, sy
 
 
-def psf_table(z: float, R: float, W: int, pitch: float = 1e-6, wavelength: float = 633e-9):
+def psf_table(z: float, R: float, W: int, pitch: float = 1e-6, wavelength: float = 633e-9,
+              sx: int = 0, sy: int = 0):
     lib = _load()
     out = np.zeros(2 * W * W)
-    lib.oracle_psf_table(z, R, W, pitch, wavelength, _p(out))
+    lib.oracle_psf_table(z, R, W, sx, sy, pitch, wavelength, _p(out))
     return _complex_from(out, (W, W))
 
 
@@ -178,15 +196,16 @@ def round_value(v: float, dtype: int) -> float:
 
 def build_lut(prm: LutParams) -> Lut:
     lib = _load()
-    z, R, W, Nr = lut_geometry(prm)
-    off = np.zeros(prm.n_depth + 1, dtype=np.int64)
+    z, R, W, Nr, sx, sy = lut_geometry(prm)
+    nt = len(z)
+    off = np.zeros(nt + 1, dtype=np.int64)
     off[1:] = np.cumsum(Nr)
     total = int(off[-1])
     idx = np.zeros(total, dtype=np.int32)
     val = np.zeros(2 * total)
-    lib.oracle_build_lut(prm.wavelength, prm.pitch, prm.n_depth, prm.levels, _p(z), _p(R), _p(W),
-                         _p(Nr), _p(off), prm.value_dtype, _p(idx), _p(val))
-    return Lut(prm, z, R, W, Nr, off, idx, val.view(np.complex128))
+    lib.oracle_build_lut(prm.wavelength, prm.pitch, nt, prm.levels, _p(z), _p(R), _p(W),
+                         _p(Nr), _p(sx), _p(sy), _p(off), prm.value_dtype, _p(idx), _p(val))
+    return Lut(prm, z, R, W, Nr, off, idx, val.view(np.complex128), sx, sy)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -194,9 +213,9 @@ def build_lut(prm: LutParams) -> Lut:
 # ----------------------------------------------------------------------------------------------
 @dataclass
 class Quantized:
-    x: np.ndarray  # int32 global pixel column, multiple of 2^L
+    x: np.ndarray  # int32 global pixel column, multiple of 2^L (any pixel with phase tables)
     y: np.ndarray  # int32 global pixel row
-    d: np.ndarray  # int32 plane, -1 = invalid
+    d: np.ndarray  # int32 table (plane, or plane and phase), -1 = invalid
     a: np.ndarray  # float64 amplitude
 
 
@@ -207,7 +226,7 @@ def quantize(pts: np.ndarray, prm: LutParams) -> Quantized:
     qx = np.zeros(n, np.int32); qy = np.zeros(n, np.int32); qd = np.zeros(n, np.int32)
     qa = np.zeros(n)
     lib.oracle_quantize(_p(pts), n, prm.pitch, prm.z_min, prm.z_max, prm.n_depth, prm.levels,
-                        _p(qx), _p(qy), _p(qd), _p(qa))
+                        int(prm.phases), _p(qx), _p(qy), _p(qd), _p(qa))
     return Quantized(qx, qy, qd, qa)
 
 

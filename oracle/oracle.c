@@ -15,7 +15,8 @@
  *   oracle_haar_inverse  orthonormal, Mallat layout) and its inverse (Sec. 2, step 3).
  *   oracle_select        Sec. 2, step 1: keep the N_r strongest coefficients.
  *   oracle_quantize      depth discretisation (Sec. 2, step 1) and the 2^L position grid that
- *                        makes the level-scaled shift of Eq.(2) an integer.
+ *                        makes the level-scaled shift of Eq.(2) an integer; with phase tables,
+ *                        the pixel grid and the point's position inside its 2^L block.
  *   oracle_superpose     Eq.(2) with the sub-hologram coordinate shift x'_j = x_j - s N_h
  *                        (Sec. 2, large-scale procedure, steps 2-3).
  *
@@ -83,12 +84,14 @@ void oracle_direct(const double *pts, int64_t n, int32_t nx, int32_t ny, int64_t
  *   dz  = (z_max - z_min) / n_depth,  plane d sits at the cell centre z_d = z_min + (d + 1/2) dz
  *   R_d = z_d tan(theta_max) / p     PSF radius in pixels (the circ() support)
  *   W_d = table side: the smallest multiple of 2^(L+1) that holds the disk, W_d >= 2 floor(R_d) + 2,
- *         so that the table centre W_d / 2 is a multiple of 2^L.
+ *         so that the table centre W_d / 2 is a multiple of 2^L.  With phase tables the disk's
+ *         centre may sit up to 2^L - 1 pixels right of / below the table centre, so the table
+ *         must hold a disk around any of those centres: W_d >= 2 floor(R_d) + 2^(L+1).
  *   N_r = ceil(gamma pi R_d^2) clamped to [1, W_d^2]; gamma >= 1 keeps all W_d^2 coefficients.
  * Returns 0, or -1 if a table would exceed max_window.
  * ---------------------------------------------------------------------------------------- */
 int oracle_lut_geometry(double wavelength, double pitch, double z_min, double z_max, int32_t n_depth,
-                        int32_t levels, int32_t max_window, double gamma,
+                        int32_t levels, int32_t max_window, double gamma, int32_t phases,
                         double *z, double *R, int32_t *W, int64_t *Nr)
 {
     const double tan_t = tan_theta_max(wavelength, pitch);
@@ -97,7 +100,7 @@ int oracle_lut_geometry(double wavelength, double pitch, double z_min, double z_
     for (int32_t d = 0; d < n_depth; d++) {
         z[d] = z_min + ((double)d + 0.5) * dz;
         R[d] = z[d] * tan_t / pitch;
-        int32_t need = 2 * (int32_t)floor(R[d]) + 2;
+        int32_t need = 2 * (int32_t)floor(R[d]) + (phases ? q : 2);
         W[d] = ((need + q - 1) / q) * q;
         if (W[d] > max_window) return -1;
         int64_t all = (int64_t)W[d] * W[d];
@@ -115,17 +118,20 @@ int oracle_lut_geometry(double wavelength, double pitch, double z_min, double z_
 }
 
 /* ------------------------------------------------------------------------------------------
- * PSF table (Sec. 2, step 1):  T[r][q] = exp(i 2 pi / lambda * sqrt(((q-c)p)^2 + ((r-c)p)^2 + z^2))
- * when (q-c)^2 + (r-c)^2 < R^2 (circ(c) = 1 iff c < 1), else 0.  c = W / 2.
+ * PSF table (Sec. 2, step 1):  T[r][q] = exp(i 2 pi / lambda * sqrt(((q-cx)p)^2 + ((r-cy)p)^2 + z^2))
+ * when (q-cx)^2 + (r-cy)^2 < R^2 (circ(c) = 1 iff c < 1), else 0.  The disk's centre is
+ * (cx, cy) = (W/2 + sx, W/2 + sy): sx = sy = 0 for the paper's one table per plane; a phase table
+ * holds the PSF of a point sx columns right of and sy rows below its 2^L block's corner.
  * The phase is taken modulo one revolution before the cosine and sine: the same value, but the
  * thousands of whole revolutions no longer cost FP64 digits.
  * ---------------------------------------------------------------------------------------- */
-void oracle_psf_table(double z, double R, int32_t W, double pitch, double wavelength, double *T)
+void oracle_psf_table(double z, double R, int32_t W, int32_t sx, int32_t sy, double pitch,
+                      double wavelength, double *T)
 {
-    const int32_t c = W / 2;
+    const int32_t cx = W / 2 + sx, cy = W / 2 + sy;
     for (int32_t r = 0; r < W; r++) {
         for (int32_t q = 0; q < W; q++) {
-            const double dq = (double)(q - c), dr = (double)(r - c);
+            const double dq = (double)(q - cx), dr = (double)(r - cy);
             double re = 0.0, im = 0.0;
             if (dq * dq + dr * dr < R * R) {
                 /* phase 2 pi dist / lambda, whole revolutions removed first (an exact step) */
@@ -276,23 +282,34 @@ double oracle_round_value(double v, int32_t dtype)
 }
 
 /* ------------------------------------------------------------------------------------------
- * LUT build (Sec. 2, step 1): for every plane, PSF table -> L-level Haar -> N_r strongest
- * coefficients -> values rounded to the storage dtype.  Canonical layout: plane d owns
- * entries [off[d], off[d+1]), sorted by flat table index.  off has n_depth + 1 entries and is
- * computed by the caller from Nr (off[0] = 0).
+ * LUT build (Sec. 2, step 1): for every table, PSF table -> L-level Haar -> N_r strongest
+ * coefficients -> values rounded to the storage dtype.  Canonical layout: table d owns
+ * entries [off[d], off[d+1]), sorted by flat table index.  off has n_tables + 1 entries and is
+ * computed by the caller from Nr (off[0] = 0).  Table d's disk centre is shifted by
+ * (sx[d], sy[d]) pixels from the table centre (all zero without phase tables).
  * ---------------------------------------------------------------------------------------- */
-void oracle_build_lut(double wavelength, double pitch, int32_t n_depth, int32_t levels,
+void oracle_build_lut(double wavelength, double pitch, int32_t n_tables, int32_t levels,
                       const double *z, const double *R, const int32_t *W, const int64_t *Nr,
-                      const int64_t *off, int32_t value_dtype, int32_t *idx, double *val)
+                      const int32_t *sx, const int32_t *sy, const int64_t *off, int32_t value_dtype,
+                      int32_t *idx, double *val)
 {
-    for (int32_t d = 0; d < n_depth; d++) {
+    for (int32_t d = 0; d < n_tables; d++) {
         double *T = (double *)malloc(sizeof(double) * 2 * (size_t)W[d] * (size_t)W[d]);
-        oracle_psf_table(z[d], R[d], W[d], pitch, wavelength, T);
+        oracle_psf_table(z[d], R[d], W[d], sx[d], sy[d], pitch, wavelength, T);
         oracle_haar_forward(T, W[d], W[d], levels);
         oracle_select(T, W[d], Nr[d], idx + off[d], val + 2 * off[d]);
         for (int64_t k = 2 * off[d]; k < 2 * off[d + 1]; k++) val[k] = oracle_round_value(val[k], value_dtype);
         free(T);
     }
+}
+
+/* floor(v / 2^s) for any sign of v. */
+static int64_t floor_shift(int64_t v, int32_t s)
+{
+    const int64_t q = (int64_t)1 << s;
+    int64_t r = v / q;
+    if (r * q > v) r -= 1;
+    return r;
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -301,11 +318,15 @@ void oracle_build_lut(double wavelength, double pitch, int32_t n_depth, int32_t 
  * z -> plane d = floor((z - z_min) / dz), with z = z_max going to the last plane (Sec. 2,
  * step 1, depth discretisation).  Points with z outside [z_min, z_max], a non-finite
  * coordinate, or a snapped position beyond +-2^30 pixels get d = -1 and contribute nothing.
+ * With phase tables (phases = 1) x, y go to the nearest pixel instead (ties upward) and the
+ * table index is d 4^L + (y mod 2^L) 2^L + (x mod 2^L): the table of the point's position
+ * inside its 2^L block (mod taken towards minus infinity).
  * ---------------------------------------------------------------------------------------- */
 void oracle_quantize(const double *pts, int64_t n, double pitch, double z_min, double z_max,
-                     int32_t n_depth, int32_t levels, int32_t *qx, int32_t *qy, int32_t *qd, double *qa)
+                     int32_t n_depth, int32_t levels, int32_t phases, int32_t *qx, int32_t *qy,
+                     int32_t *qd, double *qa)
 {
-    const double B = (double)(1 << levels);
+    const double B = (double)(phases ? 1 : (1 << levels));
     const double dz = (z_max - z_min) / (double)n_depth;
     for (int64_t k = 0; k < n; k++) {
         const double x = pts[4 * k], y = pts[4 * k + 1], z = pts[4 * k + 2], a = pts[4 * k + 3];
@@ -322,17 +343,13 @@ void oracle_quantize(const double *pts, int64_t n, double pitch, double z_min, d
         if (d > n_depth - 1) d = n_depth - 1;
         qx[k] = (int32_t)sx;
         qy[k] = (int32_t)sy;
+        if (phases) {
+            const int64_t px = (int64_t)sx - (floor_shift((int64_t)sx, levels) << levels);
+            const int64_t py = (int64_t)sy - (floor_shift((int64_t)sy, levels) << levels);
+            d = (int32_t)(((int64_t)d << (2 * levels)) + (py << levels) + px);
+        }
         qd[k] = d;
     }
-}
-
-/* floor(v / 2^s) for any sign of v. */
-static int64_t floor_shift(int64_t v, int32_t s)
-{
-    const int64_t q = (int64_t)1 << s;
-    int64_t r = v / q;
-    if (r * q > v) r -= 1;
-    return r;
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -341,13 +358,15 @@ static int64_t floor_shift(int64_t v, int32_t s)
  * (level-l bands of size (ny>>l) x (nx>>l): H at (0, nx>>l), V at (ny>>l, 0), D at (ny>>l, nx>>l);
  * S^(L) at (0,0)), accumulated in place.
  *
+ * The table of point j is table d = pd[j] (its plane, or its plane and phase).
  * A kept entry at flat index idx of plane d's W x W table sits at table row/col (row, col).  Its
  * level l and band follow from the Mallat layout: the first l = 1..L with row >= W>>l or
  * col >= W>>l, else the scaling band at level L.  The table's pixel (0,0) lies at global pixel
  * (x_j - W/2, y_j - W/2); at level l that origin moves by 2^-l (the shift weight alpha of Eq.(2)),
  * so the entry lands at band position (m + floor(oy / 2^l), n + floor(ox / 2^l)) with
  * ox = x_j - W/2 - X0, oy = y_j - W/2 - Y0.  Entries landing outside the sub-hologram are dropped.
- * x_j, y_j are first floored to multiples of 2^L (the identity for quantised points).
+ * x_j, y_j are first floored to multiples of 2^L (the identity for points snapped to the 2^L
+ * grid; for a point with a phase table, the corner of its 2^L block, the table carrying the rest).
  * ---------------------------------------------------------------------------------------- */
 void oracle_superpose(int32_t levels, const int32_t *W, const int64_t *off, const int32_t *idx,
                       const double *val, const int32_t *px, const int32_t *py, const int32_t *pd,

@@ -24,7 +24,7 @@ def _params(orc, **kw):
 def _check_against_oracle(orc, gp, op):
     lut = cgh.wasabi_build_lut(gp)
     info = lut.info()
-    z, R, W, Nr = orc.lut_geometry(op)
+    z, R, W, Nr, _, _ = orc.lut_geometry(op)
     np.testing.assert_array_equal(info["W"], W)
     np.testing.assert_array_equal(info["Nr"], Nr)
     np.testing.assert_array_equal(info["z"], z)
@@ -75,7 +75,7 @@ def test_gamma_one_keeps_everything(orc):
     gp, op = _params(orc, gamma=1.0, levels=2)
     lut = cgh.wasabi_build_lut(gp)
     off, idx, val = lut.export()
-    _, _, W, _ = orc.lut_geometry(op)
+    _, _, W, _, _, _ = orc.lut_geometry(op)
     for d in range(op.n_depth):
         np.testing.assert_array_equal(idx[off[d]:off[d + 1]], np.arange(int(W[d]) ** 2))
 

@@ -12,7 +12,7 @@ P = 1e-6
 def test_plane_geometry_hand_worked(orc):
     (rows,) = read_golden("lut_geometry_2048.txt")
     prm = orc.LutParams(n_depth=64, levels=3, gamma=0.05)
-    z, R, W, Nr = orc.lut_geometry(prm)
+    z, R, W, Nr, _, _ = orc.lut_geometry(prm)
     for d, z_um, R_px, Wd, nr in rows:
         d = int(d)
         assert abs(z[d] * 1e6 - z_um) < 1e-9
@@ -21,7 +21,7 @@ def test_plane_geometry_hand_worked(orc):
     assert W.min() == 80 and W.max() == 1008
     assert np.all(W % 16 == 0)
     # gamma >= 1 keeps every coefficient of the table
-    _, _, W1, Nr1 = orc.lut_geometry(orc.LutParams(n_depth=64, levels=3, gamma=1.0))
+    _, _, W1, Nr1, _, _ = orc.lut_geometry(orc.LutParams(n_depth=64, levels=3, gamma=1.0))
     np.testing.assert_array_equal(Nr1, W1.astype(np.int64) ** 2)
     with pytest.raises(ValueError):
         orc.lut_geometry(orc.LutParams(n_depth=64, levels=3, max_window=512))
