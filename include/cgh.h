@@ -83,6 +83,13 @@ int cgh_direct(const double *pts_dev, int64_t n, int32_t nx, int32_t ny, int64_t
  * W_d^2 when gamma >= 1) are kept, values rounded to `value_dtype`.  Magnitude ties are broken
  * by the library's internal coefficient order, so two correct LUTs may differ at the threshold.
  * The PSF phase, transform and selection are computed in FP64.
+ * Phase tables (phases = 1): Eq.(2) moves a table by whole 2^L blocks, so a plane's single table
+ * places only points on the 2^L grid.  With phase tables every plane gets 4^L tables, one per
+ * position (sx, sy) of a point inside its 2^L x 2^L block (0 <= sx, sy < 2^L): table
+ * t = d 4^L + sy 2^L + sx holds the PSF centred on pixel (W_d/2 + sx, W_d/2 + sy), with
+ * W_d the smallest multiple of 2^(L+1) >= 2 floor(R_d) + 2^(L+1) so that every shifted disk fits,
+ * and points are placed on any pixel.  N_r(d) is the same for the 4^L tables.  Without phase
+ * tables there is one table per plane (t = d).  The LUT then takes 4^L times the memory.
  * ------------------------------------------------------------------------------------------- */
 typedef struct {
     double wavelength;   /* metres, 0 < wavelength < 2 pitch                                  */
@@ -95,6 +102,9 @@ typedef struct {
                             W_d up to about 7900 (L = 3) or 4000 (L = 4) pixels               */
     int32_t value_dtype; /* CGH_F32, CGH_F16 or CGH_BF16                                       */
     double gamma;        /* selectivity, > 0                                                   */
+    int32_t phases;      /* 0: one table per plane (points snapped to the 2^L grid);
+                            1: 4^L phase tables per plane (points snapped to the pixel grid);
+                            n_depth 4^L <= 2^20                                                */
 } wasabi_lut_params;
 
 typedef struct wasabi_lut wasabi_lut; /* opaque, library-owned, device-resident */
@@ -103,20 +113,22 @@ typedef struct wasabi_lut wasabi_lut; /* opaque, library-owned, device-resident 
  * Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP.  On error *out is NULL. */
 int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, void *stream);
 
-/* Build the device LUT from host arrays in the canonical layout: plane d owns entries
- * [off[d], off[d+1]) (off: n_depth + 1 int64, off[0] = 0), each an int32 flat table index
- * idx = row * W_d + col of the plane's Mallat-layout table (sorted ascending, no repeats) and a
- * complex value val[2k], val[2k+1] (double, rounded here to value_dtype).  The plane geometry
- * comes from `prm`; gamma is ignored.  Synchronous.  Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
+/* Build the device LUT from host arrays in the canonical layout: table t owns entries
+ * [off[t], off[t+1]) (off: n_tables + 1 int64, off[0] = 0; n_tables = n_depth, or n_depth 4^L
+ * with phase tables), each an int32 flat table index idx = row * W_t + col of the table's
+ * Mallat-layout coefficients (sorted ascending, no repeats) and a complex value val[2k],
+ * val[2k+1] (double, rounded here to value_dtype).  The table geometry comes from `prm`; gamma is
+ * ignored.  Synchronous.  Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
 int wasabi_lut_import(const wasabi_lut_params *prm, const int64_t *off_host,
                       const int32_t *idx_host, const double *val_host, wasabi_lut **out);
 
-/* Sizes of the LUT.  Any output pointer may be NULL; per-plane arrays hold n_depth values (host). */
-int wasabi_lut_info(const wasabi_lut *lut, int32_t *n_depth, int64_t *total_entries,
+/* Sizes of the LUT.  Any output pointer may be NULL; per-table arrays hold n_tables values
+ * (host): the plane's z, R, W and N_r of every table. */
+int wasabi_lut_info(const wasabi_lut *lut, int32_t *n_tables, int64_t *total_entries,
                     int64_t *device_bytes, double *z_host, double *R_host, int32_t *W_host,
                     int64_t *Nr_host);
 
-/* Copy the LUT to host arrays in the canonical layout above (off: n_depth + 1, idx/val: total
+/* Copy the LUT to host arrays in the canonical layout above (off: n_tables + 1, idx/val: total
  * entries; val as double pairs holding the stored, rounded values).  Synchronous. */
 int wasabi_lut_export(const wasabi_lut *lut, int64_t *off_host, int32_t *idx_host, double *val_host);
 
@@ -124,9 +136,11 @@ int wasabi_lut_export(const wasabi_lut *lut, int64_t *off_host, int32_t *idx_hos
 void wasabi_lut_free(wasabi_lut *lut);
 
 /* ---------------------------------------------------------------------------------------------
- * Points for the wavelet path.  x, y: global pixel column / row, multiples of 2^L (superposition
- * floors other values to the grid); depth: plane index, -1 = invalid (contributes nothing);
- * a: amplitude.
+ * Points for the wavelet path.  x, y: global pixel column / row; depth: table index (the plane,
+ * or with phase tables d 4^L + (y mod 2^L) 2^L + (x mod 2^L)), -1 = invalid (contributes
+ * nothing); a: amplitude.  The superposition places the table at the corner of the point's 2^L
+ * block (x, y floored to multiples of 2^L): exact for points on the 2^L grid and, with phase
+ * tables, for any pixel.
  * ------------------------------------------------------------------------------------------- */
 typedef struct {
     int32_t x, y, depth;
@@ -135,7 +149,9 @@ typedef struct {
 
 /* Depth discretisation (Sec. 2, step 1) and the 2^L position grid that makes the level-scaled
  * shift of Eq.(2) an integer: x/pitch and y/pitch go to the nearest multiple of 2^L (ties
- * upward), z to plane floor((z - z_min) / dz) (z = z_max -> the last plane).  A point with z
+ * upward; with phase tables to the nearest pixel, and depth is the table of the point's plane
+ * and position inside its 2^L block), z to plane floor((z - z_min) / dz) (z = z_max -> the
+ * last plane).  A point with z
  * outside [z_min, z_max], a non-finite value, or a snapped position beyond +-2^30 gets depth -1.
  *   pts_dev : device, n x 4 double {x, y, z, a} metres (as for cgh_direct).
  *   out_dev : device, n wasabi_point.

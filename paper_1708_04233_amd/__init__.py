@@ -46,7 +46,7 @@ class _LutParams(ctypes.Structure):
                 ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
                 ("n_depth", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("max_window", ctypes.c_int32), ("value_dtype", ctypes.c_int32),
-                ("gamma", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("phases", ctypes.c_int32)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -193,10 +193,12 @@ class LutParams:
     max_window: int = 1024
     gamma: float = 0.05
     value_dtype: int = F32
+    phases: int = 0   # 1: 4^L phase tables per plane, points on any pixel
 
     def c(self) -> _LutParams:
         return _LutParams(self.wavelength, self.pitch, self.z_min, self.z_max, self.n_depth,
-                          self.levels, self.max_window, self.value_dtype, self.gamma)
+                          self.levels, self.max_window, self.value_dtype, self.gamma,
+                          int(self.phases))
 
 
 class Lut:
@@ -223,14 +225,14 @@ class Lut:
         W = np.zeros(n, np.int32); Nr = np.zeros(n, np.int64)
         _check(lib.wasabi_lut_info(self.handle, None, None, None, z.ctypes.data, R.ctypes.data,
                                    W.ctypes.data, Nr.ctypes.data))
-        return dict(n_depth=n, total_entries=tot.value, device_bytes=dev_bytes.value, z=z, R=R,
+        return dict(n_tables=n, total_entries=tot.value, device_bytes=dev_bytes.value, z=z, R=R,
                     W=W, Nr=Nr)
 
     def export(self):
         """(off, idx, val): canonical layout, val complex128 holding the stored values."""
         inf = self.info()
         tot = inf["total_entries"]
-        off = np.zeros(inf["n_depth"] + 1, np.int64)
+        off = np.zeros(inf["n_tables"] + 1, np.int64)
         idx = np.zeros(max(tot, 1), np.int32)
         val = np.zeros(2 * max(tot, 1))
         _check(load().wasabi_lut_export(self.handle, off.ctypes.data, idx.ctypes.data, val.ctypes.data))

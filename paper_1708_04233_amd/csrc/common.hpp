@@ -132,18 +132,23 @@ struct DenseRow {
 
 }  // namespace cgh
 
+// Tables: one per plane, or with phase tables 4^L per plane (table t = d 4^L + sy 2^L + sx holds
+// plane d's PSF centred sx columns right of and sy rows below the table centre).  Every per-table
+// vector below has n_tables entries.
 struct wasabi_lut {
     wasabi_lut_params prm;
     int device;
     int L, B;
+    int P;                            // tables per plane: 1, or 4^L with phase tables
+    int n_tables;                     // n_depth * P
     std::vector<double> z, R;
     std::vector<int32_t> W;
     std::vector<int64_t> Nr;
-    std::vector<int64_t> entry_off;   // n_depth + 1
+    std::vector<int64_t> entry_off;   // n_tables + 1
     std::vector<cgh::DepthDesc> desc_host;
     int64_t total_entries;
     int32_t max_span_px;              // largest occupied extent of any plane, pixels
-    cgh::DepthDesc *desc;             // device, n_depth
+    cgh::DepthDesc *desc;             // device, n_tables
     int32_t *blk_off;                 // device
     void *values;                     // device: float2 (F32) or uint32 packed pair (F16, BF16)
     uint16_t *keys;                   // device

@@ -97,9 +97,10 @@ __host__ __device__ inline int64_t block_to_flat(int br, int bc, int code, int W
 }
 
 // ---- PSF table + in-block forward Haar ------------------------------------------------------
+// The disk's centre is (W/2 + sx, W/2 + sy): sx = sy = 0 but for phase tables.
 template <int L>
-__global__ __launch_bounds__(256) void psf_haar_kernel(int W, int nb, double z, double R2,
-                                                       double pitch, double lambda,
+__global__ __launch_bounds__(256) void psf_haar_kernel(int W, int nb, int sx, int sy, double z,
+                                                       double R2, double pitch, double lambda,
                                                        double2 *coef, uint32_t *magq)
 {
     constexpr int B = 1 << L, BB = B * B;
@@ -117,8 +118,8 @@ __global__ __launch_bounds__(256) void psf_haar_kernel(int W, int nb, double z, 
         double2 v = make_double2(0.0, 0.0);
         if (blk < nblk) {
             const int br = (int)(blk / nb), bc = (int)(blk % nb);
-            const double dr = (double)(br * B + code / B - c);
-            const double dq = (double)(bc * B + code % B - c);
+            const double dr = (double)(br * B + code / B - c - sy);
+            const double dq = (double)(bc * B + code % B - c - sx);
             if (dq * dq + dr * dr < R2) {
                 const double dist = sqrt((dq * pitch) * (dq * pitch) + (dr * pitch) * (dr * pitch) + z * z);
                 const double t = dist / lambda;  // revolutions; whole ones dropped below
@@ -399,7 +400,8 @@ __global__ __launch_bounds__(256) void dense_scatter_kernel(const DenseJob *jobs
 
 // ---- quantisation ---------------------------------------------------------------------------
 __global__ void quantize_kernel(const double4 *pts, int64_t n, double pitch, double z_min,
-                                double z_max, double dz, int n_depth, int L, wasabi_point *out)
+                                double z_max, double dz, int n_depth, int L, int phases,
+                                wasabi_point *out)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -409,7 +411,7 @@ __global__ void quantize_kernel(const double4 *pts, int64_t n, double pitch, dou
     q.y = 0;
     q.depth = -1;
     q.a = (float)p.w;
-    const double B = (double)(1 << L);
+    const double B = phases ? 1.0 : (double)(1 << L);  // snapping grid: 2^L, or the pixel
     if (isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w) && p.z >= z_min &&
         p.z <= z_max) {
         const double sx = B * floor(p.x / pitch / B + 0.5);
@@ -419,6 +421,10 @@ __global__ void quantize_kernel(const double4 *pts, int64_t n, double pitch, dou
             if (d > n_depth - 1) d = n_depth - 1;
             q.x = (int32_t)sx;
             q.y = (int32_t)sy;
+            if (phases) {  // the table of the point's position inside its 2^L block
+                const int px = q.x & ((1 << L) - 1), py = q.y & ((1 << L) - 1);
+                d = (d << (2 * L)) + (py << L) + px;
+            }
             q.depth = d;
         }
     }
@@ -455,7 +461,7 @@ size_t value_bytes(int vt) { return vt == CGH_F32 ? 8 : 4; }
 // Dense layout for large gamma: row spans from the block offsets, then a scatter kernel.
 int build_dense(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
 {
-    const int n = lut->prm.n_depth, B = lut->B, BB = B * B;
+    const int n = lut->n_tables, B = lut->B, BB = B * B;
     lut->dense = lut->prm.gamma >= kDenseGamma;
     if (!lut->dense) return CGH_OK;
     std::vector<DenseRow> rows;
@@ -531,7 +537,7 @@ int build_dense(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
 // Fill the occupied block ranges, the per-plane value bound and the device descriptors.
 int finish_lut(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
 {
-    const int n = lut->prm.n_depth;
+    const int n = lut->n_tables;
     lut->max_span_px = 0;
     std::vector<float> cmax(n, 0.0f);
     {
@@ -589,7 +595,7 @@ int finish_lut(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
 // Allocate the LUT object and its device arrays for the geometry already in lut->W / lut->Nr.
 int alloc_lut(wasabi_lut *lut)
 {
-    const int n = lut->prm.n_depth;
+    const int n = lut->n_tables;
     lut->entry_off.assign(n + 1, 0);
     lut->desc_host.resize(n);
     int64_t blk_total = 0;
@@ -629,6 +635,8 @@ wasabi_lut *new_lut(const wasabi_lut_params *prm)
     lut->prm = *prm;
     lut->L = prm->levels;
     lut->B = 1 << prm->levels;
+    lut->P = 1;
+    lut->n_tables = 0;
     lut->desc = nullptr;
     lut->blk_off = nullptr;
     lut->values = nullptr;
@@ -645,7 +653,7 @@ wasabi_lut *new_lut(const wasabi_lut_params *prm)
 }
 
 template <int L>
-void launch_psf_haar(int W, int nb, double z, double R2, double pitch, double lambda,
+void launch_psf_haar(int W, int nb, int sx, int sy, double z, double R2, double pitch, double lambda,
                      double2 *coef, uint32_t *magq, hipStream_t s)
 {
     constexpr int BB = 1 << (2 * L);
@@ -653,7 +661,7 @@ void launch_psf_haar(int W, int nb, double z, double R2, double pitch, double la
     const int64_t nblk = (int64_t)nb * nb;
     const unsigned grid = (unsigned)((nblk + G - 1) / G);
     ProfScope prof("psf_haar", s);
-    hipLaunchKernelGGL(psf_haar_kernel<L>, dim3(grid), dim3(256), 0, s, W, nb, z, R2, pitch,
+    hipLaunchKernelGGL(psf_haar_kernel<L>, dim3(grid), dim3(256), 0, s, W, nb, sx, sy, z, R2, pitch,
                        lambda, coef, magq);
 }
 
@@ -676,7 +684,7 @@ extern "C" int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, 
         wasabi_lut_free(lut);
         return rc;
     }
-    const int n = prm->n_depth, L = lut->L;
+    const int n = lut->n_tables, L = lut->L;
     int64_t coef_total = 0;
     std::vector<int64_t> coef_off(n + 1, 0);
     for (int d = 0; d < n; ++d) coef_off[d + 1] = coef_off[d] + (int64_t)lut->W[d] * lut->W[d];
@@ -698,16 +706,17 @@ extern "C" int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, 
     std::vector<SelPlane> planes(n);
     for (int d = 0; d < n && !rc; ++d) {
         const int W = lut->W[d], nb = W / lut->B;
+        const int ph = d % lut->P, sx = ph % lut->B, sy = ph / lut->B;  // table shift (phase tables)
         const double R2 = lut->R[d] * lut->R[d];
         double2 *c = coef + coef_off[d];
         uint32_t *m2 = mag2 + coef_off[d];
         switch (L) {
-        case 1: launch_psf_haar<1>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
-        case 2: launch_psf_haar<2>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
-        case 3: launch_psf_haar<3>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
-        case 4: launch_psf_haar<4>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
-        case 5: launch_psf_haar<5>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
-        default: launch_psf_haar<6>(W, nb, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 1: launch_psf_haar<1>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 2: launch_psf_haar<2>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 3: launch_psf_haar<3>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 4: launch_psf_haar<4>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        case 5: launch_psf_haar<5>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
+        default: launch_psf_haar<6>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = fail(CGH_EHIP, "psf_haar_kernel: %s", hipGetErrorString(e));
@@ -775,7 +784,7 @@ extern "C" int wasabi_lut_import(const wasabi_lut_params *prm, const int64_t *of
     wasabi_lut *lut = new_lut(&p);
     rc = lut_geometry(lut);
     lut->prm.gamma = prm->gamma;
-    const int n = prm->n_depth, L = lut->L, B = lut->B;
+    const int n = lut->n_tables, L = lut->L, B = lut->B;
     if (!rc && off[0] != 0) rc = fail(CGH_EINVAL, "off[0] must be 0");
     for (int d = 0; d < n && !rc; ++d) {
         const int64_t cnt = off[d + 1] - off[d];
@@ -856,13 +865,13 @@ extern "C" int wasabi_lut_import(const wasabi_lut_params *prm, const int64_t *of
     return CGH_OK;
 }
 
-extern "C" int wasabi_lut_info(const wasabi_lut *lut, int32_t *n_depth, int64_t *total_entries,
+extern "C" int wasabi_lut_info(const wasabi_lut *lut, int32_t *n_tables, int64_t *total_entries,
                                int64_t *device_bytes, double *z, double *R, int32_t *W, int64_t *Nr)
 {
     using namespace cgh;
     if (!lut) return fail(CGH_EINVAL, "lut is NULL");
-    const int n = lut->prm.n_depth;
-    if (n_depth) *n_depth = n;
+    const int n = lut->n_tables;
+    if (n_tables) *n_tables = n;
     if (total_entries) *total_entries = lut->total_entries;
     if (device_bytes) *device_bytes = (int64_t)lut->device_bytes;
     for (int d = 0; d < n; ++d) {
@@ -878,7 +887,7 @@ extern "C" int wasabi_lut_export(const wasabi_lut *lut, int64_t *off, int32_t *i
 {
     using namespace cgh;
     if (!lut || !off || !idx || !val) return fail(CGH_EINVAL, "NULL argument");
-    const int n = lut->prm.n_depth, L = lut->L, B = lut->B, BS = block_stride(L);
+    const int n = lut->n_tables, L = lut->L, B = lut->B, BS = block_stride(L);
     const int64_t total = lut->total_entries;
     const int vt = lut->prm.value_dtype;
     std::vector<uint16_t> keys(total);
@@ -959,7 +968,8 @@ extern "C" int wasabi_quantize(const wasabi_lut *lut, const double *pts, int64_t
     if (blocks > INT32_MAX) return fail(CGH_EINVAL, "n too large");
     ProfScope prof("quantize", (hipStream_t)stream);
     hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(threads), 0, (hipStream_t)stream,
-                       (const double4 *)pts, n, p.pitch, p.z_min, p.z_max, dz, p.n_depth, lut->L, out);
+                       (const double4 *)pts, n, p.pitch, p.z_min, p.z_max, dz, p.n_depth, lut->L,
+                       p.phases, out);
     CGH_CHECK_LAUNCH("quantize_kernel");
     return CGH_OK;
 }

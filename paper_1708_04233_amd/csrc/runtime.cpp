@@ -114,12 +114,17 @@ int validate_params(const wasabi_lut_params *prm)
     if (prm->value_dtype < CGH_F32 || prm->value_dtype > CGH_BF16)
         return fail(CGH_EINVAL, "unknown value_dtype");
     if (!(prm->gamma > 0) || !std::isfinite(prm->gamma)) return fail(CGH_EINVAL, "gamma must be > 0");
+    if (prm->phases != 0 && prm->phases != 1) return fail(CGH_EINVAL, "phases must be 0 or 1");
+    if (prm->phases && ((int64_t)prm->n_depth << (2 * prm->levels)) > (INT64_C(1) << 20))
+        return fail(CGH_EINVAL, "n_depth * 4^L phase tables exceed 2^20");
     return CGH_OK;
 }
 
 // Sec. 2, step 1: planes at the centres of n_depth equal depth cells; PSF radius from the
 // largest diffraction angle of the pitch (sin theta = lambda / 2p); table side W_d the smallest
-// multiple of 2^(L+1) holding the disk (so the table centre is on the 2^L grid); N_r = gamma pi R^2.
+// multiple of 2^(L+1) holding the disk (so the table centre is on the 2^L grid; with phase tables
+// the disk around any centre shifted by less than 2^L pixels right / down); N_r = gamma pi R^2.
+// With phase tables each plane's values repeat for its 4^L tables.
 int lut_geometry(wasabi_lut *lut)
 {
     const wasabi_lut_params &p = lut->prm;
@@ -130,15 +135,18 @@ int lut_geometry(wasabi_lut *lut)
     const int q = 1 << (p.levels + 1);
     const int B = 1 << p.levels;
     const int key_room = 65536 / block_stride(p.levels);  // blocks per row that keys can address
-    lut->z.resize(n);
-    lut->R.resize(n);
-    lut->W.resize(n);
-    lut->Nr.resize(n);
+    lut->P = p.phases ? 1 << (2 * p.levels) : 1;
+    lut->n_tables = n * lut->P;
+    const int P = lut->P, nt = lut->n_tables;
+    lut->z.resize(nt);
+    lut->R.resize(nt);
+    lut->W.resize(nt);
+    lut->Nr.resize(nt);
     for (int d = 0; d < n; d++) {
         const double z = p.z_min + ((double)d + 0.5) * dz;
         const double R = z * tan_t / p.pitch;
         if (!(R < 1e6)) return fail(CGH_EINVAL, "plane %d: PSF radius too large", d);
-        const int64_t need = 2 * (int64_t)std::floor(R) + 2;
+        const int64_t need = 2 * (int64_t)std::floor(R) + (p.phases ? q : 2);
         const int64_t W = ((need + q - 1) / q) * q;
         if (W > p.max_window)
             return fail(CGH_EINVAL, "plane %d needs a %lld-pixel table > max_window %d", d,
@@ -155,10 +163,12 @@ int lut_geometry(wasabi_lut *lut)
             if (nr < 1) nr = 1;
             if (nr > all) nr = all;
         }
-        lut->z[d] = z;
-        lut->R[d] = R;
-        lut->W[d] = (int32_t)W;
-        lut->Nr[d] = nr;
+        for (int t = d * P; t < (d + 1) * P; ++t) {
+            lut->z[t] = z;
+            lut->R[t] = R;
+            lut->W[t] = (int32_t)W;
+            lut->Nr[t] = nr;
+        }
     }
     return CGH_OK;
 }

@@ -1,23 +1,30 @@
 // Wavelet-domain superposition (Eq.(2)), inverse Haar transform (Sec. 2, step 3) and the
 // sub-hologram procedure (Sec. 2, large-scale steps 2-4) for gfx950.
 //
-// Tiles.  The window is cut into 64 x 64 pixel tiles (ragged at the right and bottom edges).  With
-// points and window origins on the 2^L grid, every coefficient a point contributes belongs to one
-// aligned 2^L x 2^L Haar block of the window, so a tile's coefficients are exactly the
-// coefficients of its own blocks.  One workgroup owns one tile and keeps its coefficients in LDS,
-// block by block (each block in its own L-level Mallat layout, padded block stride BS(L)).
+// Tables.  A point adds the kept coefficients of one LUT table: its depth plane's, or with phase
+// tables the table of its plane and of its position inside its 2^L block.  Below, "plane" means
+// such a table; a point's `depth` field is its table index.
 //
-// Binning.  bin_count / scan / bin_fill build, for every tile, the list of points whose
-// occupied table area overlaps it (global atomics only on the per-tile counters).
+// Tiles.  The window is cut into 64 x 64 pixel tiles (ragged at the right and bottom edges).  With
+// window origins on the 2^L grid and every table placed at the corner of its point's 2^L block,
+// every coefficient a point contributes belongs to one aligned 2^L x 2^L Haar block of the window,
+// so a tile's coefficients are exactly the coefficients of its own blocks.  One workgroup owns one
+// tile and keeps its coefficients in LDS, block by block (each block in its own L-level Mallat
+// layout, block stride BS(L)).
+//
+// Binning.  The points are sorted by (plane, row band) and, for every list cell (a tile or a
+// square of tiles), listed when their occupied table area overlaps it.
 //
 // Superposition.  For a (tile, point) pair the table blocks that fall in the tile form a
-// rectangle; its entries are one contiguous LUT range per block row.  A wave walks the
-// concatenated ranges 64 entries at a time and adds a_j * c into LDS with ds_add_f32 at
-// row_base(block row) + key, so no global atomics touch the wavelet field.
+// rectangle; in the sparse layout its entries are one contiguous LUT range per block row, walked
+// by a wave that adds a_j * c into LDS as packed fixed-point (re, im) words with one 64-bit integer
+// add; in the dense layout each wave sums whole table blocks into its own coefficients in FP32
+// registers.  No global atomics touch the wavelet field.
 //
-// Output.  MODE_PSI scatters the tile's coefficients into the Mallat layout of the window;
-// MODE_FUSED inverts each block in LDS and writes pixels, so the wavelet field never reaches HBM.
-// idwt_kernel gathers a tile from a Mallat-layout field, inverts it in LDS and writes pixels.
+// Output.  MODE_PSI writes the tile's coefficients into the Mallat layout of the window;
+// MODE_FUSED inverts the tile's blocks on chip and writes pixels, so the wavelet field never
+// reaches HBM.  idwt_kernel gathers a tile from a Mallat-layout field, inverts it in LDS and
+// writes pixels.
 #include <algorithm>
 #include <cstdlib>
 #include <mutex>
@@ -59,10 +66,10 @@ __device__ inline void tile_of(int b, const TileGeom &g, int &ty, int &tx)
 }
 
 // List cells touched by the occupied part of point p's table; false if none.
-__device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, int n_depth, int L,
+__device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, int n_tables, int L,
                                  const TileGeom &g, int &ty0, int &ty1, int &tx0, int &tx1)
 {
-    if (p.depth < 0 || p.depth >= n_depth) return false;
+    if (p.depth < 0 || p.depth >= n_tables) return false;
     const DepthDesc d = desc[p.depth];
     if (d.br1 <= d.br0) return false;
     const int64_t B = 1 << L;
@@ -87,14 +94,14 @@ constexpr int kDepthChunk = 8192;     // points per workgroup in the plane sort
 //      window row of a (tile, point) pair is tile_y - point_y + W/2, which then advances in step
 //      across all tiles, and the band stays in L2 while they use it. ----
 struct SortKey {
-    int n_depth;
+    int n_tables;
     int nyb;        // row bands per plane
     int64_t y0;     // row of band 0 (window origin minus the largest half table)
 };
 
 __device__ inline int sort_key(const wasabi_point &p, const SortKey &k)
 {
-    if (p.depth < 0 || p.depth >= k.n_depth) return k.n_depth * k.nyb;
+    if (p.depth < 0 || p.depth >= k.n_tables) return k.n_tables * k.nyb;
     int64_t b = ((int64_t)p.y - k.y0) >> 6;
     b = b < 0 ? 0 : (b >= k.nyb ? k.nyb - 1 : b);
     return p.depth * k.nyb + (int)b;
@@ -105,7 +112,7 @@ __global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *p
                                                            SortKey key, int32_t *counts)
 {
     extern __shared__ int hist[];  // nbins (LDS variant)
-    const int nbins = key.n_depth * key.nyb + 1;
+    const int nbins = key.n_tables * key.nyb + 1;
     if (LDS) {
         for (int i = threadIdx.x; i < nbins; i += 1024) hist[i] = 0;
         __syncthreads();
@@ -131,7 +138,7 @@ __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point 
                                                              wasabi_point *sorted)
 {
     extern __shared__ int sh[];  // LDS variant: local count[nbins] then base[nbins] (64-bit)
-    const int nbins = key.n_depth * key.nyb + 1;
+    const int nbins = key.n_tables * key.nyb + 1;
     int *cnt = sh;
     unsigned long long *base = (unsigned long long *)(sh + ((nbins + 1) & ~1));
     const int64_t j0 = (int64_t)blockIdx.x * kDepthChunk;
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point 
 // ---- per-cell point lists (counting sort by list cell; a cell is a square of tiles) -------------------------------------------
 template <bool LDS>
 __global__ __launch_bounds__(256) void bin_count_kernel(const wasabi_point *pts, int64_t n,
-                                                        const DepthDesc *desc, int n_depth, int L,
+                                                        const DepthDesc *desc, int n_tables, int L,
                                                         TileGeom g, int32_t *counts)
 {
     __shared__ int hist[LDS ? kMaxLdsTiles : 1];
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(const wasabi_point *pts,
     }
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int ty0, ty1, tx0, tx1;
-    if (j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1)) {
+    if (j < n && footprint(pts[j], desc, n_tables, L, g, ty0, ty1, tx0, tx1)) {
         for (int ty = ty0; ty < ty1; ++ty)
             for (int tx = tx0; tx < tx1; ++tx) {
                 if (LDS) atomicAdd(&hist[ty * g.nlx + tx], 1);
@@ -187,7 +194,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(const wasabi_point *pts,
 
 template <bool LDS>
 __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, int64_t n,
-                                                       const DepthDesc *desc, int n_depth, int L,
+                                                       const DepthDesc *desc, int n_tables, int L,
                                                        TileGeom g, unsigned long long *cursor,
                                                        int32_t *list)
 {
@@ -196,7 +203,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
     const int ntiles = g.nlx * g.nly;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int ty0 = 0, ty1 = 0, tx0 = 0, tx1 = 0;
-    const bool has = j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1);
+    const bool has = j < n && footprint(pts[j], desc, n_tables, L, g, ty0, ty1, tx0, tx1);
     if (LDS) {
         for (int i = threadIdx.x; i < ntiles; i += 256) cnt[i] = 0;
         __syncthreads();
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
 constexpr int kChunk = 64;
 
 __global__ __launch_bounds__(kChunk) void bin_count_matrix_kernel(const wasabi_point *pts, int64_t n,
-                                                                  const DepthDesc *desc, int n_depth,
+                                                                  const DepthDesc *desc, int n_tables,
                                                                   int L, TileGeom g, int nwg,
                                                                   int32_t *mat)
 {
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(kChunk) void bin_count_matrix_kernel(const wasabi_p
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * kChunk + threadIdx.x;
     int ty0, ty1, tx0, tx1;
-    if (j < n && footprint(pts[j], desc, n_depth, L, g, ty0, ty1, tx0, tx1))
+    if (j < n && footprint(pts[j], desc, n_tables, L, g, ty0, ty1, tx0, tx1))
         for (int ty = ty0; ty < ty1; ++ty)
             for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&hist[ty * g.nlx + tx], 1);
     __syncthreads();
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(kChunk) void bin_count_matrix_kernel(const wasabi_p
 }
 
 __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_point *pts, int64_t n,
-                                                                 const DepthDesc *desc, int n_depth,
+                                                                 const DepthDesc *desc, int n_tables,
                                                                  int L, TileGeom g, int nwg,
                                                                  const int64_t *moff, int32_t *list)
 {
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_po
     const int np = (int)min((int64_t)kChunk, n - j0);
     {
         int ty0 = 0, ty1 = 0, tx0 = 0, tx1 = 0;
-        if (threadIdx.x < np && !footprint(pts[j0 + threadIdx.x], desc, n_depth, L, g, ty0, ty1, tx0, tx1))
+        if (threadIdx.x < np && !footprint(pts[j0 + threadIdx.x], desc, n_tables, L, g, ty0, ty1, tx0, tx1))
             ty0 = ty1 = tx0 = tx1 = 0;
         fp[threadIdx.x][0] = ty0;
         fp[threadIdx.x][1] = ty1;
@@ -376,7 +383,7 @@ struct TileArgs {
     const void *dense;          // dense layout values (or NULL)
     int64_t dense_zero;         // first of kDenseZero zero values in `dense`
     const DenseRow *dense_rows; // dense layout block-row spans
-    int n_depth;
+    int n_tables;
     int *plane_done;            // plane pacing: tiles that finished plane d (NULL = off)
     int pace_slack;             // a tile starts plane d once all tiles finished plane d - slack
 };
@@ -1158,7 +1165,7 @@ void dense_tile_kernel(TileArgs a)
             // the table bands being read at any moment stay in L2.  Every wait is bounded: after
             // kPaceSpin polls a tile stops waiting for good, so progress never depends on it.
             int *bnd = (int *)sbuf;  // plane d owns list positions [bnd[d], bnd[d + 1])
-            const int nd = a.n_depth;
+            const int nd = a.n_tables;
             for (int d = threadIdx.x; d <= nd; d += kDenseThreads) bnd[d] = 0;
             __syncthreads();
             for (int64_t p = p0 + threadIdx.x; p < p1; p += kDenseThreads) {
@@ -1341,7 +1348,7 @@ namespace {
 // Bins of the plane sort: (plane, 64-row band of the point's y) pairs plus one for invalid points.
 int sort_bands(const wasabi_lut *lut, const TileGeom &g)
 {
-    const int nd = lut->prm.n_depth;
+    const int nd = lut->n_tables;
     int nyb = (int)std::min<int64_t>(((int64_t)g.ny + 2 * lut->max_span_px + 63) / 64, 4096);
     if ((int64_t)nyb * nd + 1 > (INT64_C(1) << 26)) nyb = std::max(1, (1 << 26) / nd - 1);
     return nyb;
@@ -1369,9 +1376,9 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
 {
     const int64_t ntiles = (int64_t)g.nlx * g.nly;  // lists
     const int64_t bound = pair_bound(lut, n, g);
-    const int nd = lut->prm.n_depth, L = lut->L;
+    const int nd = lut->n_tables, L = lut->L;
     SortKey key;
-    key.n_depth = nd;
+    key.n_tables = nd;
     key.y0 = g.oy - lut->max_span_px;
     key.nyb = sort_bands(lut, g);
     const int nbins = nd * key.nyb + 1;
@@ -1517,7 +1524,7 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.dense = lut ? lut->dense_values : nullptr;
     a.dense_zero = lut ? lut->dense_zero : 0;
     a.dense_rows = lut ? lut->dense_rows : nullptr;
-    a.n_depth = lut ? lut->prm.n_depth : 0;
+    a.n_tables = lut ? lut->n_tables : 0;
     a.plane_done = nullptr;
     a.pace_slack = 5;
     return a;
@@ -1594,10 +1601,10 @@ int launch_window(const wasabi_lut *lut, const Binned &b, int64_t ox, int64_t oy
     static const int pace_env = getenv("CGH_PACE") ? atoi(getenv("CGH_PACE")) : 1;
     static const int slack_env = getenv("CGH_PACE_SLACK") ? atoi(getenv("CGH_PACE_SLACK")) : 5;
     int rc;
-    if (allow_pace && pace_env && lut->dense && b.ordered && lut->L >= 3 && lut->prm.n_depth <= kPaceMaxPlanes &&
+    if (allow_pace && pace_env && lut->dense && b.ordered && lut->L >= 3 && lut->n_tables <= kPaceMaxPlanes &&
         resident_capacity(lut->L, lut->prm.value_dtype, mode) >= (int64_t)g.ntx * g.nty) {
         int *done;
-        const size_t bytes = sizeof(int) * (size_t)lut->prm.n_depth * kPaceCounters;
+        const size_t bytes = sizeof(int) * (size_t)lut->n_tables * kPaceCounters;
         if ((rc = sc.alloc((void **)&done, bytes))) return rc;
         CGH_TRY_HIP(hipMemsetAsync(done, 0, bytes, s));
         a.plane_done = done;
@@ -1662,7 +1669,7 @@ int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_
     TileGeom g = make_geom(0, 0, nx, ny);
     choose_lists(g);
     const int64_t ntiles = (int64_t)g.nlx * g.nly;  // lists
-    const int64_t nbins = (int64_t)lut->prm.n_depth * sort_bands(lut, g) + 1;
+    const int64_t nbins = (int64_t)lut->n_tables * sort_bands(lut, g) + 1;
     auto r = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
     auto scan = [&](int64_t count) { return r(8 * ((count + 1023) / 1024)); };
     int64_t t = r(4 * ntiles) + r(8 * (ntiles + 1)) + r(8 * ntiles) + r(8 * ntiles) + r(4 * pair_bound(lut, n, g)) +

@@ -24,7 +24,8 @@ def _params(orc, **kw):
 def _check_against_oracle(orc, gp, op):
     lut = cgh.wasabi_build_lut(gp)
     info = lut.info()
-    z, R, W, Nr, _, _ = orc.lut_geometry(op)
+    z, R, W, Nr, sx, sy = orc.lut_geometry(op)
+    assert info["n_tables"] == len(z)
     np.testing.assert_array_equal(info["W"], W)
     np.testing.assert_array_equal(info["Nr"], Nr)
     np.testing.assert_array_equal(info["z"], z)
@@ -32,9 +33,9 @@ def _check_against_oracle(orc, gp, op):
     off, idx, val = lut.export()
     assert off[-1] == Nr.sum()
     swapped = 0
-    for d in range(op.n_depth):
-        C = orc.haar_forward(orc.psf_table(z[d], R[d], int(W[d]), op.pitch, op.wavelength),
-                             op.levels).ravel()
+    for d in range(len(z)):
+        C = orc.haar_forward(orc.psf_table(z[d], R[d], int(W[d]), op.pitch, op.wavelength,
+                                           sx=int(sx[d]), sy=int(sy[d])), op.levels).ravel()
         mag2 = np.abs(C) ** 2
         g_idx = idx[off[d]:off[d + 1]]
         assert len(g_idx) == Nr[d] and np.all(np.diff(g_idx) > 0)
@@ -55,6 +56,13 @@ def _check_against_oracle(orc, gp, op):
 @pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6])
 def test_build_matches_oracle_small(orc, levels):
     gp, op = _params(orc, levels=levels, max_window=256, z_max=120e-6)
+    _check_against_oracle(orc, gp, op)
+
+
+@pytest.mark.parametrize("levels,gamma", [(1, 0.3), (2, 0.3), (3, 0.2), (3, 0.6), (4, 0.1)])
+def test_phase_tables_match_oracle(orc, levels, gamma):
+    """4^L tables per plane, each the plane's PSF moved inside its 2^L block."""
+    gp, op = _params(orc, levels=levels, gamma=gamma, n_depth=2, max_window=256, phases=1)
     _check_against_oracle(orc, gp, op)
 
 
@@ -95,6 +103,17 @@ def test_import_export_round_trip(orc, dtype):
     again = cgh.wasabi_lut_import(gp, *o1).export()
     for a, b in zip(o1, again):
         np.testing.assert_array_equal(a, b)
+
+
+def test_phase_import_export_round_trip(orc):
+    gp, op = _params(orc, levels=2, gamma=0.3, n_depth=3, phases=1)
+    ref = orc.build_lut(op)
+    lut = cgh.wasabi_lut_import(gp, ref.off, ref.idx, ref.val)
+    assert lut.info()["n_tables"] == 3 * 16
+    off, idx, val = lut.export()
+    np.testing.assert_array_equal(off, ref.off)
+    np.testing.assert_array_equal(idx, ref.idx)
+    np.testing.assert_array_equal(val, ref.val)
 
 
 def test_import_rejects_bad_tables(orc):
