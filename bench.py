@@ -104,9 +104,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload, kernel):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by
-    the copy calibration), or None when none were taken for this kernel source and workload."""
+def counter_traffic(workload, kernel, launches=1):
+    """HBM bytes per launch (times `launches`) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (scaled by the copy calibration), or None when none were taken for this kernel source
+    and workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             table = json.load(f)
@@ -115,7 +116,7 @@ def counter_traffic(workload, kernel):
     e = table.get(workload + "|" + kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
-    return e["traffic_bytes_per_launch"]
+    return e["traffic_bytes_per_launch"] * launches
 
 
 def psnr(u, ref):
@@ -431,14 +432,22 @@ def run_large(args, torch, cgh):
                 "sub": sub, "ms": round(ms_sub, 2),
                 "kernels_ms_total": {k: round(v[0], 3) for k, v in sk.items()},
                 "launches": {k: v[1] for k, v in sk.items()},
-                "idwt_roofline": {"bound": "hbm", "achieved": round(16 * nx * ny / (idwt_ms * 1e-3) / 1e9, 1),
+                "idwt_roofline": {"symbol": "idwt_kernel<%d>" % L, "bound": "hbm",
+                                  "achieved": round(16 * nx * ny / (idwt_ms * 1e-3) / 1e9, 1),
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": round(16 * nx * ny / (idwt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "traffic_all_launches": counter_traffic("%s@%.2f-sub%d" % (w["name"], g, sub),
+                                                                          "idwt_kernel<%d>" % L, sk["idwt"][1]),
                                   "algorithmic_bytes": 16 * nx * ny},
-                "superpose_roofline": {"bound": "hbm",
+                "superpose_roofline": {"symbol": "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt),
+                                       "bound": "hbm",
                                        "achieved": round(algo / (sup_ms * 1e-3) / 1e9, 1),
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": round(algo / (sup_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                       "traffic_all_launches": counter_traffic(
+                                           "%s@%.2f-sub%d" % (w["name"], g, sub),
+                                           "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt),
+                                           sk["tile_superpose"][1]),
                                        "algorithmic_bytes": algo}}
         results["gamma_%.2f" % g] = res
         log(args.workload, res)
