@@ -119,6 +119,20 @@ def counter_traffic(workload, kernel, launches=1):
     return e["traffic_bytes_per_launch"] * launches
 
 
+def image_psnr(torch, cgh, u, ref, depths):
+    """Image-domain PSNR (the paper judges holograms by their reconstructions): both complex64
+    holograms on the GPU are propagated back by -z for each depth z (angular spectrum) and their
+    intensities compared, 10 log10(max I_ref^2 / mean (I - I_ref)^2), pooled over the depths."""
+    num = den = peak = 0.0
+    for z in depths:
+        a = cgh.cgh_propagate(u, -z).abs().square().double()
+        b = cgh.cgh_propagate(ref, -z).abs().square().double()
+        num += float((a - b).square().sum())
+        den += a.numel()
+        peak = max(peak, float(b.max()) ** 2)
+    return float("inf") if num == 0 else 10 * np.log10(peak / (num / den))
+
+
 def psnr(u, ref):
     mse = float(np.mean(np.abs(u - ref) ** 2))
     return float("inf") if mse == 0 else 10 * np.log10(float(np.max(np.abs(ref)) ** 2) / mse)
@@ -144,10 +158,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lut", choices=["f32", "f16", "bf16"], default="f32",
                     help="LUT value storage (the 2048^2 workload is specified in FP32)")
-    ap.add_argument("--workload", choices=["2048", "16384", "65536", "serve", "phases"], default="2048",
+    ap.add_argument("--workload", choices=["2048", "16384", "65536", "serve", "phases", "wrp"], default="2048",
                     help="2048: the headline line; 16384 / 65536: the large holograms; serve: the "
                          "hologram server under Poisson load; phases: points off the 2^L grid, one "
-                         "table per plane against phase tables")
+                         "table per plane against phase tables; wrp: a deep scene through a wavefront "
+                         "recording plane")
     ap.add_argument("--serve-jobs", type=int, default=None,
                     help="jobs per serving run (default 200 beside the headline line, 1000 for --workload serve)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -178,6 +193,8 @@ def main():
         return run_precision(args, torch, cgh)
     if args.workload == "phases":
         return run_phases(args, torch, cgh)
+    if args.workload == "wrp":
+        return run_wrp(args, torch, cgh)
     if args.workload != "2048":
         return run_large(args, torch, cgh)
     w = WASABI_2048
@@ -258,6 +275,13 @@ def main():
     ref = cgh.cgh_direct(snapped_t, nx, ny, window=cgh.CIRC, out_dtype=torch.complex128).cpu().numpy()
     p40, p05 = psnr(u40, ref), psnr(u05, ref)
     log("psnr gamma40 %.2f dB, gamma 0.05 %.2f dB; direct %.3f ms" % (p40, p05, ms_direct))
+    # image-domain PSNR: reconstructions at three depths of the scene
+    rec_depths = (0.3e-3, 0.8e-3, 1.3e-3)
+    u40_t = torch.from_numpy(u40.astype(np.complex64)).cuda()
+    u05_t = torch.from_numpy(u05.astype(np.complex64)).cuda()
+    img40 = image_psnr(torch, cgh, u40_t, ud, rec_depths)
+    img05 = image_psnr(torch, cgh, u05_t, ud, rec_depths)
+    del u40_t, u05_t
 
     # ---- roofline of the dominant kernel (tile_fused) ----------------------------------------
     off, idx, _ = lut40.export()
@@ -306,6 +330,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "global_batch": n, "hologram": [ny, nx],
                    "planes": w["n_depth"], "levels": L, "gamma": g40, "psnr_db": round(p40, 2),
+                   "image_psnr_db": round(img40, 2), "image_psnr_depths_mm": [z * 1e3 for z in rec_depths],
                    "lut_values": args.lut, "lut_entries": int(info40["total_entries"]),
                    "lut_build_ms": round(build40_ms, 1), "path": "quantize+bin+fused superpose/inverse"},
         "ms_per_step_untraced": round(ms_untraced, 4),
@@ -313,7 +338,7 @@ def main():
         "direct": {"value": round(mpp / (ms_direct * 1e-3), 1), "ms_per_step": round(ms_direct, 4),
                    "window": "circ", "dtype": "f32 sums, f64 phase", "psnr_db": "inf"},
         "speedup_vs_direct": round(ms_direct / ms_step, 3),
-        "workload_gamma": {"gamma": w["gamma"], "psnr_db": round(p05, 2),
+        "workload_gamma": {"gamma": w["gamma"], "psnr_db": round(p05, 2), "image_psnr_db": round(img05, 2),
                            "value": round(mpp / (ms_g05 * 1e-3), 1), "ms_per_step": round(ms_g05, 4),
                            "lut_build_ms": round(build05_ms, 1)},
         "separate_kernels": {"ms_per_step": round(ms_split, 4),
@@ -536,6 +561,87 @@ def run_phases(args, torch, cgh):
            "direct": {"ms_per_step": round(ms_direct, 4), "value": round(mpp / (ms_direct * 1e-3), 1),
                       "window": "circ", "psnr_db": "inf"},
            "speedup_vs_direct": round(ms_direct / main["ms_per_step"], 3)}
+    print(json.dumps(out), flush=True)
+
+
+def run_wrp(args, torch, cgh):
+    """A deep scene through a wavefront recording plane (WRP): 2048^2, N = 10^4 points on the 2^3
+    grid at z ~ U[5.0, 5.5] mm, where a point's PSF covers most of the hologram.  The WRP sits at
+    4.9 mm; the LUT covers the depths 0.1 .. 0.6 mm from it (64 planes, L = 3, FP32).
+      WRP + WASABI : wasabi_hologram_wrp (WASABI on the WRP, then one propagation over 4.9 mm);
+      WRP + direct : the circ() direct sum on the WRP, then the same propagation (the WRP method
+                     with exact PSFs: the reference for WASABI's error);
+      direct       : the circ() direct sum on the hologram plane itself.
+    Quality: complex-field PSNR and image-domain PSNR (reconstructions at 5.1, 5.25, 5.4 mm) of
+    WRP + WASABI against WRP + direct."""
+    nx = ny = 2048
+    n, L, z_wrp = 10_000, 3, 4.9e-3
+    rng = np.random.default_rng(5)
+    pts_np = np.stack([8 * np.floor(rng.uniform(0, 256, n)) * 1e-6, 8 * np.floor(rng.uniform(0, 256, n)) * 1e-6,
+                       rng.uniform(5.0e-3, 5.5e-3, n), rng.uniform(0, 1, n)], axis=1)
+    pts = torch.from_numpy(pts_np).cuda()
+    mpp = nx * ny * n / 1e6
+    g40 = args.gamma if args.gamma is not None else gamma40()
+    runs = {}
+    u = torch.empty((ny, nx), dtype=torch.complex64, device="cuda")
+    ref = None
+    for g in (g40, 0.05):
+        prm = cgh.LutParams(z_min=0.1e-3, z_max=0.6e-3, n_depth=64, levels=L, gamma=g, max_window=1024)
+        lut = cgh.wasabi_build_lut(prm)
+        info = lut.info()
+        if ref is None:
+            rel = pts_np.copy()
+            rel[:, 2] -= z_wrp
+            q = cgh.wasabi_quantize(lut, torch.from_numpy(rel).cuda()).cpu().numpy()
+            ok = q[:, 2] >= 0
+            on_wrp = np.ascontiguousarray(np.stack([q[ok, 0] * 1e-6, q[ok, 1] * 1e-6, info["z"][q[ok, 2]],
+                                                    pts_np[ok, 3]], axis=1))
+            on_wrp_t = torch.from_numpy(on_wrp).cuda()
+            absolute = on_wrp.copy()
+            absolute[:, 2] += z_wrp
+            absolute_t = torch.from_numpy(absolute).cuda()
+            uw = torch.empty((ny, nx), dtype=torch.complex64, device="cuda")
+
+            def wrp_direct():
+                cgh.cgh_direct(on_wrp_t, nx, ny, window=cgh.CIRC, out=uw)
+                cgh.cgh_propagate(uw, z_wrp, out=uw)
+            ms_wrp_direct = timed(wrp_direct, args.steps, 1, torch)
+            wrp_direct()
+            ref = uw.clone()
+            ud = torch.empty((ny, nx), dtype=torch.complex64, device="cuda")
+            ms_direct = timed(lambda: cgh.cgh_direct(absolute_t, nx, ny, window=cgh.CIRC, out=ud),
+                              max(2, args.steps // 4), 1, torch)
+        ms = timed(lambda: cgh.wasabi_hologram_wrp(lut, pts, z_wrp, nx, ny, u=u), args.steps, 1, torch)
+        cgh.wasabi_hologram_wrp(lut, pts, z_wrp, nx, ny, u=u)
+        torch.cuda.synchronize()
+        cgh.cgh_profile_reset()
+        cgh.cgh_profile_enable(True)
+        cgh.wasabi_hologram_wrp(lut, pts, z_wrp, nx, ny, u=u)
+        torch.cuda.synchronize()
+        cgh.cgh_profile_enable(False)
+        kern = {nm: round(cgh.cgh_profile_query(nm)[0], 4) for nm in ("quantize", "bin", "tile_fused", "propagate")}
+        cgh.cgh_profile_reset()
+        runs["wrp_wasabi_gamma_%.2f" % g] = {
+            "gamma": g, "ms_per_step": round(ms, 4), "value": round(mpp / (ms * 1e-3), 1), "kernels_ms": kern,
+            "psnr_db_vs_wrp_direct": round(psnr(u.cpu().numpy().astype(np.complex128),
+                                                ref.cpu().numpy().astype(np.complex128)), 2),
+            "image_psnr_db_vs_wrp_direct": round(image_psnr(torch, cgh, u, ref, (5.1e-3, 5.25e-3, 5.4e-3)), 2),
+            "lut_entries": int(info["total_entries"])}
+        log("wrp", g, runs["wrp_wasabi_gamma_%.2f" % g])
+        del lut
+    main = runs["wrp_wasabi_gamma_%.2f" % g40]
+    out = {"metric": METRIC, "value": main["value"], "unit": "Mpixel·points/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": main["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "wrp-2048x2048-n10000-z5.0-5.5mm-L3-64planes", "global_batch": n,
+                      "hologram": [ny, nx], "z_wrp_mm": z_wrp * 1e3, "gamma": g40, "levels": L,
+                      "planes": 64, "lut_depths_mm": [0.1, 0.6]},
+           "runs": runs,
+           "wrp_direct": {"ms_per_step": round(ms_wrp_direct, 4), "value": round(mpp / (ms_wrp_direct * 1e-3), 1)},
+           "direct": {"ms_per_step": round(ms_direct, 4), "value": round(mpp / (ms_direct * 1e-3), 1),
+                      "window": "circ"},
+           "speedup_vs_direct": round(ms_direct / main["ms_per_step"], 3),
+           "speedup_vs_wrp_direct": round(ms_wrp_direct / main["ms_per_step"], 3)}
     print(json.dumps(out), flush=True)
 
 

@@ -197,6 +197,33 @@ int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, in
                           int64_t ld_u, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Numerical propagation (the reconstruction Sec. 3 judges holograms by) and the wavefront
+ * recording plane (the conclusion's next step).
+ *
+ * cgh_propagate: angular-spectrum propagation of a complex field by `distance` metres (either
+ * sign), the field taken as periodic: u_out = IFFT2(FFT2(u_in) H) with
+ * H(fx, fy) = exp(i 2 pi distance sqrt(1/lambda^2 - fx^2 - fy^2)) where fx^2 + fy^2 < 1/lambda^2,
+ * 0 elsewhere; fx = k / (nx pitch), fy = k / (ny pitch), k in FFT order (0 .. n/2-1, -n/2 .. -1).
+ *   u_in, u_out : device, ny x nx complex64 row-major, contiguous; u_out may equal u_in.
+ *   nx, ny      : powers of two in [64, 8192].
+ * FP32 transforms; twiddles and the transfer function's phase from FP64 angles.  Takes 16 nx ny
+ * bytes of scratch from the stream-ordered pool.  Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP.
+ *
+ * wasabi_hologram_wrp: the hologram of points far from the hologram plane through a wavefront
+ * recording plane z_wrp metres from it.  Every point's depth is taken from the WRP (z - z_wrp,
+ * which must lie in the LUT's [z_min, z_max]; others contribute nothing), WASABI computes the
+ * field on the WRP (as wasabi_quantize + wasabi_hologram_fused at origin (0, 0)), and
+ * cgh_propagate carries it over z_wrp to the hologram plane, in place in u.
+ *   pts_dev : device, n x 4 double {x, y, z, a} metres (as for wasabi_quantize).
+ *   u_dev   : device, ny x nx complex64 row-major, contiguous; overwritten.
+ *   nx, ny  : powers of two in [64, 8192].
+ * Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
+int cgh_propagate(const void *u_in_dev, void *u_out_dev, int32_t nx, int32_t ny, double distance,
+                  double pitch, double wavelength, void *stream);
+int wasabi_hologram_wrp(const wasabi_lut *lut, const double *pts_dev, int64_t n, double z_wrp,
+                        int32_t nx, int32_t ny, void *u_dev, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Hologram server: a queue of hologram jobs served with continuous batching.
  *
  * Every job is one hologram (Sec. 2): its points are snapped (wasabi_quantize) and superposed and

@@ -12,6 +12,8 @@ the C ABI in ``include/cgh.h``:
   wasabi_idwt             inverse Haar transform (Sec. 2 step 3)
   wasabi_hologram         sub-hologram procedure (Sec. 2, large-scale steps 2-4)
   wasabi_hologram_fused   the same, tile by tile in on-chip memory
+  cgh_propagate           angular-spectrum propagation (numerical reconstruction)
+  wasabi_hologram_wrp     WASABI on a wavefront recording plane, then propagation
   Server                  cgh_server_*: hologram jobs with continuous batching under a memory budget
 """
 from __future__ import annotations
@@ -100,6 +102,8 @@ def load() -> ctypes.CDLL:
         "wasabi_idwt": ([P, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram": ([P, P, I64, I64, I64, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram_fused": ([P, P, I64, I64, I64, I32, I32, P, I64, P], ctypes.c_int),
+        "cgh_propagate": ([P, P, I32, I32, D, D, D, P], ctypes.c_int),
+        "wasabi_hologram_wrp": ([P, P, I64, D, I32, I32, P, P], ctypes.c_int),
         "cgh_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(P)], ctypes.c_int),
         "cgh_server_submit": ([P, ctypes.POINTER(_Job), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "cgh_server_wait": ([P, ctypes.c_uint64, I32, ctypes.POINTER(_Result)], ctypes.c_int),
@@ -324,6 +328,29 @@ def wasabi_hologram_fused(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, 
     _check(load().wasabi_hologram_fused(lut.handle, _dev(q, "points", torch.int32, (n, 4)), n, ox,
                                         oy, nx, ny, ctypes.c_void_p(u.data_ptr()), u.stride(0),
                                         _stream()))
+    return u
+
+
+def cgh_propagate(u: torch.Tensor, distance: float, pitch: float = 1e-6, wavelength: float = 633e-9,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """Angular-spectrum propagation of the complex64 field u (ny, nx) by `distance` metres."""
+    ny, nx = u.shape
+    _dev(u, "u", torch.complex64)
+    out = torch.empty_like(u) if out is None else out
+    _dev(out, "out", torch.complex64, (ny, nx))
+    _check(load().cgh_propagate(ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()), nx, ny,
+                                distance, pitch, wavelength, _stream()))
+    return out
+
+
+def wasabi_hologram_wrp(lut: Lut, pts: torch.Tensor, z_wrp: float, nx: int, ny: int,
+                        u: torch.Tensor | None = None) -> torch.Tensor:
+    """Hologram through a wavefront recording plane z_wrp metres away; pts (n, 4) float64 on the GPU."""
+    n = pts.shape[0]
+    u = torch.empty((ny, nx), dtype=torch.complex64, device=pts.device) if u is None else u
+    _dev(u, "u", torch.complex64, (ny, nx))
+    _check(load().wasabi_hologram_wrp(lut.handle, _dev(pts, "pts", torch.float64, (n, 4)), n, z_wrp, nx, ny,
+                                      ctypes.c_void_p(u.data_ptr()), _stream()))
     return u
 
 

@@ -399,13 +399,15 @@ __global__ __launch_bounds__(256) void dense_scatter_kernel(const DenseJob *jobs
 }
 
 // ---- quantisation ---------------------------------------------------------------------------
+// z_shift: subtracted from every depth first (0, or a wavefront recording plane's distance).
 __global__ void quantize_kernel(const double4 *pts, int64_t n, double pitch, double z_min,
                                 double z_max, double dz, int n_depth, int L, int phases,
-                                wasabi_point *out)
+                                double z_shift, wasabi_point *out)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double4 p = pts[j];
+    double4 p = pts[j];
+    p.z -= z_shift;
     wasabi_point q;
     q.x = 0;
     q.y = 0;
@@ -953,10 +955,10 @@ extern "C" void wasabi_lut_free(wasabi_lut *lut)
     delete lut;
 }
 
-extern "C" int wasabi_quantize(const wasabi_lut *lut, const double *pts, int64_t n,
-                               wasabi_point *out, void *stream)
+namespace cgh {
+int quantize_shifted(const wasabi_lut *lut, const double *pts, int64_t n, double z_shift,
+                     wasabi_point *out, hipStream_t stream)
 {
-    using namespace cgh;
     if (!lut) return fail(CGH_EINVAL, "lut is NULL");
     if (n < 0) return fail(CGH_EINVAL, "n < 0");
     if (n == 0) return CGH_OK;
@@ -969,7 +971,14 @@ extern "C" int wasabi_quantize(const wasabi_lut *lut, const double *pts, int64_t
     ProfScope prof("quantize", (hipStream_t)stream);
     hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(threads), 0, (hipStream_t)stream,
                        (const double4 *)pts, n, p.pitch, p.z_min, p.z_max, dz, p.n_depth, lut->L,
-                       p.phases, out);
+                       p.phases, z_shift, out);
     CGH_CHECK_LAUNCH("quantize_kernel");
     return CGH_OK;
+}
+}  // namespace cgh
+
+extern "C" int wasabi_quantize(const wasabi_lut *lut, const double *pts, int64_t n,
+                               wasabi_point *out, void *stream)
+{
+    return cgh::quantize_shifted(lut, pts, n, 0.0, out, (hipStream_t)stream);
 }

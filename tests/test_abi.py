@@ -36,3 +36,10 @@ def test_argument_validation_without_device():
     assert lib.wasabi_idwt(out, 12, 16, 3, out, 16, None) == cgh.CGH_EINVAL   # 12 % 8 != 0
     assert lib.wasabi_idwt(out, 16, 16, 3, out, 16, None) == cgh.CGH_EINVAL   # u aliases psi
     assert lib.wasabi_superpose(None, None, 0, 0, 0, 16, 16, out, None) == cgh.CGH_EINVAL
+    # propagation: NULL field, sides not powers of two or beyond 8192, bad pitch / distance
+    assert lib.cgh_propagate(None, out, 64, 64, 1e-3, 1e-6, 633e-9, None) == cgh.CGH_EINVAL
+    assert lib.cgh_propagate(out, out, 96, 64, 1e-3, 1e-6, 633e-9, None) == cgh.CGH_EINVAL
+    assert lib.cgh_propagate(out, out, 64, 16384, 1e-3, 1e-6, 633e-9, None) == cgh.CGH_EINVAL
+    assert lib.cgh_propagate(out, out, 64, 64, 1e-3, 0.0, 633e-9, None) == cgh.CGH_EINVAL
+    assert lib.cgh_propagate(out, out, 64, 64, float("inf"), 1e-6, 633e-9, None) == cgh.CGH_EINVAL
+    assert lib.wasabi_hologram_wrp(None, None, 0, 1e-3, 64, 64, out, None) == cgh.CGH_EINVAL
