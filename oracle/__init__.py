@@ -9,6 +9,7 @@ Paper: Shimobaba et al., "Fast, large-scale hologram calculation in wavelet doma
   * ``lut_geometry``    -- Sec. 2 step 1 (planes, PSF radius, N_r = gamma*pi*R^2).
   * ``psf_table``       -- Sec. 2 step 1 (u_z = exp(ikr) circ(.)).
   * ``haar_forward`` / ``haar_inverse`` -- Sec. 2 steps 1 and 3, Fig. 2(a) layout (Haar wavelet).
+  * ``dwt_forward`` / ``dwt_inverse``   -- the same for the coiflet the paper names (periodised).
   * ``build_lut``       -- Sec. 2 step 1 (transform + keep the N_r strongest coefficients).
   * ``quantize``        -- depth discretisation and the 2^L grid that Eq.(2) needs (or, with
                            phase tables, the pixel grid and the table of the point's phase).
@@ -35,6 +36,7 @@ _lib = None
 
 F32, F16, BF16, F64 = 0, 1, 2, 3
 FULL, CIRC = 0, 1
+HAAR, COIF1 = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -57,7 +59,7 @@ def _load():
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.oracle_direct.argtypes = [P, I64, I32, I32, I64, I64, D, D, I32, P]
     lib.oracle_direct.restype = None
-    lib.oracle_lut_geometry.argtypes = [D, D, D, D, I32, I32, I32, D, I32, P, P, P, P]
+    lib.oracle_lut_geometry.argtypes = [D, D, D, D, I32, I32, I32, D, I32, I32, P, P, P, P]
     lib.oracle_lut_geometry.restype = ctypes.c_int
     lib.oracle_psf_table.argtypes = [D, D, I32, I32, I32, D, D, P]
     lib.oracle_psf_table.restype = None
@@ -69,7 +71,13 @@ def _load():
     lib.oracle_select.restype = None
     lib.oracle_round_value.argtypes = [D, I32]
     lib.oracle_round_value.restype = D
-    lib.oracle_build_lut.argtypes = [D, D, I32, I32, P, P, P, P, P, P, P, I32, P, P]
+    lib.oracle_build_lut.argtypes = [D, D, I32, I32, P, P, P, P, P, P, P, I32, I32, P, P]
+    lib.oracle_filters.argtypes = [I32, P, P]
+    lib.oracle_filters.restype = I32
+    lib.oracle_dwt_forward.argtypes = [P, I32, I32, I32, I32]
+    lib.oracle_dwt_forward.restype = None
+    lib.oracle_dwt_inverse.argtypes = [P, I32, I32, I32, I32]
+    lib.oracle_dwt_inverse.restype = None
     lib.oracle_build_lut.restype = None
     lib.oracle_quantize.argtypes = [P, I64, D, D, D, I32, I32, I32, P, P, P, P]
     lib.oracle_quantize.restype = None
@@ -118,6 +126,7 @@ class LutParams:
     gamma: float = 0.05
     value_dtype: int = F32
     phases: int = 0        # 1: one table per depth and position inside the 2^L block (4^L per depth)
+    wavelet: int = 0       # 0: Haar; 1: the coiflet of order 1 (HAAR, COIF1)
 
 
 @dataclass
@@ -150,7 +159,8 @@ def lut_geometry(prm: LutParams):
     z = np.zeros(n); R = np.zeros(n)
     W = np.zeros(n, dtype=np.int32); Nr = np.zeros(n, dtype=np.int64)
     rc = lib.oracle_lut_geometry(prm.wavelength, prm.pitch, prm.z_min, prm.z_max, n, prm.levels,
-                                 prm.max_window, prm.gamma, int(prm.phases), _p(z), _p(R), _p(W), _p(Nr))
+                                 prm.max_window, prm.gamma, int(prm.phases), int(prm.wavelet), _p(z), _p(R),
+                                 _p(W), _p(Nr))
     if rc != 0:
         raise ValueError("a PSF table exceeds max_window")
     P, B = n_phases(prm), 1 << prm.levels
@@ -184,6 +194,34 @@ def haar_inverse(a: np.ndarray, levels: int) -> np.ndarray:
     return b
 
 
+def filters(wavelet: int):
+    """(lo, hi) analysis filters: Haar, or the six-tap coiflet from its closed form."""
+    lo = np.zeros(8); hi = np.zeros(8)
+    taps = _load().oracle_filters(wavelet, _p(lo), _p(hi))
+    return lo[:taps].copy(), hi[:taps].copy()
+
+
+def dwt_forward(a: np.ndarray, levels: int, wavelet: int) -> np.ndarray:
+    """Periodised orthonormal L-level 2-D transform in the Mallat layout (Haar for wavelet 0)."""
+    b = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    h, w = b.shape
+    _load().oracle_dwt_forward(_p(b), h, w, levels, wavelet)
+    return b
+
+
+def dwt_inverse(a: np.ndarray, levels: int, wavelet: int) -> np.ndarray:
+    b = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    h, w = b.shape
+    _load().oracle_dwt_inverse(_p(b), h, w, levels, wavelet)
+    return b
+
+
+def halo(prm: LutParams) -> int:
+    """Extra pixels around a window whose coiflet-domain field is inverted (5 2^L: the reach of
+    the periodised six-tap filters over L levels); 0 for Haar, whose blocks are independent."""
+    return 5 * (1 << prm.levels) if prm.wavelet == COIF1 else 0
+
+
 def select(C: np.ndarray, Nr: int):
     lib = _load()
     C = np.ascontiguousarray(C, dtype=np.complex128)
@@ -208,7 +246,7 @@ def build_lut(prm: LutParams) -> Lut:
     idx = np.zeros(total, dtype=np.int32)
     val = np.zeros(2 * total)
     lib.oracle_build_lut(prm.wavelength, prm.pitch, nt, prm.levels, _p(z), _p(R), _p(W),
-                         _p(Nr), _p(sx), _p(sy), _p(off), prm.value_dtype, _p(idx), _p(val))
+                         _p(Nr), _p(sx), _p(sy), _p(off), prm.value_dtype, int(prm.wavelet), _p(idx), _p(val))
     return Lut(prm, z, R, W, Nr, off, idx, val.view(np.complex128), sx, sy)
 
 
@@ -253,8 +291,15 @@ def superpose(lut: Lut, q: Quantized, X0: int, Y0: int, nx: int, ny: int) -> np.
 
 
 def wasabi(lut: Lut, q: Quantized, X0: int, Y0: int, nx: int, ny: int) -> np.ndarray:
-    """Hologram window (Sec. 2 large-scale steps 2-4): Eq.(2) then the inverse transform."""
-    return haar_inverse(superpose(lut, q, X0, Y0, nx, ny), lut.params.levels)
+    """Hologram window (Sec. 2 large-scale steps 2-4): Eq.(2) then the inverse transform.  With
+    coiflets the coefficients reach beyond their 2^L block, so the window is grown by a halo on
+    every side, superposed and inverted (periodised) as a whole, and its centre kept."""
+    L = lut.params.levels
+    if lut.params.wavelet == HAAR:
+        return haar_inverse(superpose(lut, q, X0, Y0, nx, ny), L)
+    H = halo(lut.params)
+    big = dwt_inverse(superpose(lut, q, X0 - H, Y0 - H, nx + 2 * H, ny + 2 * H), L, lut.params.wavelet)
+    return big[H:H + ny, H:H + nx].copy()
 
 
 # ----------------------------------------------------------------------------------------------

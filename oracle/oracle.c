@@ -13,6 +13,8 @@
  *   oracle_psf_table     Sec. 2, step 1: u_z = exp(i k r) circ(.) sampled on a W x W table.
  *   oracle_haar_forward  Sec. 2, step 1 / Fig. 2(a): L-level fast wavelet transform (Haar,
  *   oracle_haar_inverse  orthonormal, Mallat layout) and its inverse (Sec. 2, step 3).
+ *   oracle_dwt_forward   the same with coiflets, the wavelet the paper names (Sec. 2): periodised
+ *   oracle_dwt_inverse   separable filter banks; Haar's filters give the Haar transform.
  *   oracle_select        Sec. 2, step 1: keep the N_r strongest coefficients.
  *   oracle_quantize      depth discretisation (Sec. 2, step 1) and the 2^L position grid that
  *                        makes the level-scaled shift of Eq.(2) an integer; with phase tables,
@@ -86,13 +88,14 @@ void oracle_direct(const double *pts, int64_t n, int32_t nx, int32_t ny, int64_t
  *   W_d = table side: the smallest multiple of 2^(L+1) that holds the disk, W_d >= 2 floor(R_d) + 2,
  *         so that the table centre W_d / 2 is a multiple of 2^L.  With phase tables the disk's
  *         centre may sit up to 2^L - 1 pixels right of / below the table centre, so the table
- *         must hold a disk around any of those centres: W_d >= 2 floor(R_d) + 2^(L+1).
+ *         must hold a disk around any of those centres: W_d >= 2 floor(R_d) + 2^(L+1).  Coiflet
+ *         tables add a margin of 5 2^L pixels on each side.
  *   N_r = ceil(gamma pi R_d^2) clamped to [1, W_d^2]; gamma >= 1 keeps all W_d^2 coefficients.
  * Returns 0, or -1 if a table would exceed max_window.
  * ---------------------------------------------------------------------------------------- */
 int oracle_lut_geometry(double wavelength, double pitch, double z_min, double z_max, int32_t n_depth,
                         int32_t levels, int32_t max_window, double gamma, int32_t phases,
-                        double *z, double *R, int32_t *W, int64_t *Nr)
+                        int32_t wavelet, double *z, double *R, int32_t *W, int64_t *Nr)
 {
     const double tan_t = tan_theta_max(wavelength, pitch);
     const double dz = (z_max - z_min) / (double)n_depth;
@@ -101,6 +104,10 @@ int oracle_lut_geometry(double wavelength, double pitch, double z_min, double z_
         z[d] = z_min + ((double)d + 0.5) * dz;
         R[d] = z[d] * tan_t / pitch;
         int32_t need = 2 * (int32_t)floor(R[d]) + (phases ? q : 2);
+        /* coiflet tables: the periodised transform moves a coefficient up to 5 (2^L - 1) pixels
+           from its support, so a margin of 5 2^L on each side keeps the disk's coefficients from
+           wrapping round the table */
+        if (wavelet == 1) need += 2 * 5 * (1 << levels);
         W[d] = ((need + q - 1) / q) * q;
         if (W[d] > max_window) return -1;
         int64_t all = (int64_t)W[d] * W[d];
@@ -214,6 +221,85 @@ void oracle_haar_inverse(double *A, int32_t h, int32_t w, int32_t levels)
 }
 
 /* ------------------------------------------------------------------------------------------
+ * Filter banks.  wavelet 0: Haar, lo = (1, 1)/sqrt 2.  wavelet 1: the coiflet of order 1 (six
+ * taps).  The paper uses coiflets at level 3 without naming the order; the shortest is taken.
+ * Its scaling filter has the closed form (Daubechies, Ten Lectures on Wavelets, Sec. 8.2)
+ *     lo = sqrt(2)/32 (1 - s, 5 + s, 14 + 2s, 14 - 2s, 1 - s, -3 + s),   s = sqrt 7,
+ * and the wavelet filter is hi[n] = (-1)^n lo[taps - 1 - n].  Returns the number of taps.
+ * ---------------------------------------------------------------------------------------- */
+int32_t oracle_filters(int32_t wavelet, double *lo, double *hi)
+{
+    int32_t taps;
+    if (wavelet == 1) {
+        const double s = sqrt(7.0), c = sqrt(2.0) / 32.0;
+        const double f[6] = {1 - s, 5 + s, 14 + 2 * s, 14 - 2 * s, 1 - s, -3 + s};
+        taps = 6;
+        for (int32_t n = 0; n < taps; n++) lo[n] = c * f[n];
+    } else {
+        taps = 2;
+        lo[0] = lo[1] = 1.0 / sqrt(2.0);
+    }
+    for (int32_t n = 0; n < taps; n++) hi[n] = ((n & 1) ? -1.0 : 1.0) * lo[taps - 1 - n];
+    return taps;
+}
+
+/* One level of the periodised orthonormal 2-D transform of the top-left h x w region of an
+ * array with row stride `stride` (complex elements).  Along every row of length w:
+ *     a[k] = sum_t lo[t] x[(2k + t) mod w],   d[k] = sum_t hi[t] x[(2k + t) mod w],
+ * a into the left half, d into the right half; then the same along every column (a on top, d
+ * below).  So the quadrants are S (top-left, transformed again at the next level), H = detail
+ * along x (top-right), V = detail along y (bottom-left), D (bottom-right), as for Haar. */
+static void dwt_1d(const double *x, double *out, int32_t len, int64_t step, const double *lo,
+                   const double *hi, int32_t taps, int inverse)
+{
+    /* x and out: len complex values, `step` complex elements apart */
+    const int32_t half = len / 2;
+    double *t = (double *)calloc(2 * (size_t)len, sizeof(double));
+    for (int32_t k = 0; k < half; k++) {
+        for (int32_t j = 0; j < taps; j++) {
+            const int64_t n = (2 * (int64_t)k + j) % len;
+            for (int ri = 0; ri < 2; ri++) {
+                if (!inverse) {
+                    t[2 * k + ri] += lo[j] * x[2 * n * step + ri];
+                    t[2 * (half + k) + ri] += hi[j] * x[2 * n * step + ri];
+                } else {   /* the transpose: x[n] += a[k] lo[j] + d[k] hi[j] */
+                    t[2 * n + ri] += lo[j] * x[2 * (int64_t)k * step + ri] + hi[j] * x[2 * (int64_t)(half + k) * step + ri];
+                }
+            }
+        }
+    }
+    for (int32_t i = 0; i < len; i++) {
+        out[2 * (int64_t)i * step] = t[2 * i];
+        out[2 * (int64_t)i * step + 1] = t[2 * i + 1];
+    }
+    free(t);
+}
+
+void oracle_dwt_forward(double *A, int32_t h, int32_t w, int32_t levels, int32_t wavelet)
+{
+    double lo[8], hi[8];
+    const int32_t taps = oracle_filters(wavelet, lo, hi);
+    for (int32_t l = 0; l < levels; l++) {
+        const int32_t hl = h >> l, wl = w >> l;
+        for (int32_t r = 0; r < hl; r++) dwt_1d(A + 2 * (int64_t)r * w, A + 2 * (int64_t)r * w, wl, 1, lo, hi, taps, 0);
+        for (int32_t c = 0; c < wl; c++) dwt_1d(A + 2 * (int64_t)c, A + 2 * (int64_t)c, hl, w, lo, hi, taps, 0);
+    }
+}
+
+/* Inverse of oracle_dwt_forward: per level, coarsest first, columns then rows, each the transpose
+ * of the forward step (the filter bank is orthonormal). */
+void oracle_dwt_inverse(double *A, int32_t h, int32_t w, int32_t levels, int32_t wavelet)
+{
+    double lo[8], hi[8];
+    const int32_t taps = oracle_filters(wavelet, lo, hi);
+    for (int32_t l = levels - 1; l >= 0; l--) {
+        const int32_t hl = h >> l, wl = w >> l;
+        for (int32_t c = 0; c < wl; c++) dwt_1d(A + 2 * (int64_t)c, A + 2 * (int64_t)c, hl, w, lo, hi, taps, 1);
+        for (int32_t r = 0; r < hl; r++) dwt_1d(A + 2 * (int64_t)r * w, A + 2 * (int64_t)r * w, wl, 1, lo, hi, taps, 1);
+    }
+}
+
+/* ------------------------------------------------------------------------------------------
  * Shrinkage (Sec. 2, step 1): keep the N_r strongest coefficients.  Strength is |c|^2 computed
  * in FP64 and rounded to single precision (24 significant bits); equal strengths go to the lower
  * flat index (idx = row * W + col).  The rounding makes coefficients that are equal in exact
@@ -282,7 +368,8 @@ double oracle_round_value(double v, int32_t dtype)
 }
 
 /* ------------------------------------------------------------------------------------------
- * LUT build (Sec. 2, step 1): for every table, PSF table -> L-level Haar -> N_r strongest
+ * LUT build (Sec. 2, step 1): for every table, PSF table -> L-level wavelet transform (Haar, or
+ * the coiflet with wavelet = 1) -> N_r strongest
  * coefficients -> values rounded to the storage dtype.  Canonical layout: table d owns
  * entries [off[d], off[d+1]), sorted by flat table index.  off has n_tables + 1 entries and is
  * computed by the caller from Nr (off[0] = 0).  Table d's disk centre is shifted by
@@ -291,12 +378,15 @@ double oracle_round_value(double v, int32_t dtype)
 void oracle_build_lut(double wavelength, double pitch, int32_t n_tables, int32_t levels,
                       const double *z, const double *R, const int32_t *W, const int64_t *Nr,
                       const int32_t *sx, const int32_t *sy, const int64_t *off, int32_t value_dtype,
-                      int32_t *idx, double *val)
+                      int32_t wavelet, int32_t *idx, double *val)
 {
     for (int32_t d = 0; d < n_tables; d++) {
         double *T = (double *)malloc(sizeof(double) * 2 * (size_t)W[d] * (size_t)W[d]);
         oracle_psf_table(z[d], R[d], W[d], sx[d], sy[d], pitch, wavelength, T);
-        oracle_haar_forward(T, W[d], W[d], levels);
+        if (wavelet == 0)
+            oracle_haar_forward(T, W[d], W[d], levels);
+        else
+            oracle_dwt_forward(T, W[d], W[d], levels, wavelet);
         oracle_select(T, W[d], Nr[d], idx + off[d], val + 2 * off[d]);
         for (int64_t k = 2 * off[d]; k < 2 * off[d + 1]; k++) val[k] = oracle_round_value(val[k], value_dtype);
         free(T);
