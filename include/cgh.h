@@ -48,6 +48,7 @@ typedef enum {
 enum { CGH_C64 = 0, CGH_C128 = 1 };             /* complex output type                         */
 enum { CGH_F32 = 0, CGH_F16 = 1, CGH_BF16 = 2 };/* LUT value storage (rounded to nearest even) */
 enum { CGH_FULL = 0, CGH_CIRC = 1 };            /* direct-sum window                           */
+enum { CGH_HAAR = 0, CGH_COIF1 = 1 };           /* wavelet of the LUT                          */
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *cgh_last_error(void);
@@ -90,6 +91,14 @@ int cgh_direct(const double *pts_dev, int64_t n, int32_t nx, int32_t ny, int64_t
  * W_d the smallest multiple of 2^(L+1) >= 2 floor(R_d) + 2^(L+1) so that every shifted disk fits,
  * and points are placed on any pixel.  N_r(d) is the same for the 4^L tables.  Without phase
  * tables there is one table per plane (t = d).  The LUT then takes 4^L times the memory.
+ * Coiflet tables (wavelet = CGH_COIF1, the wavelet family the paper names; the order is not given
+ * and the shortest, six-tap one is used): the table is transformed by the periodised orthonormal
+ * filter bank lo = sqrt(2)/32 (1-s, 5+s, 14+2s, 14-2s, 1-s, -3+s), s = sqrt 7,
+ * hi[n] = (-1)^n lo[5-n], along rows then columns at every level (the same Mallat layout and
+ * band order as Haar), and W_d grows by 2 * 5 2^L so that no coefficient of the disk wraps round
+ * the table; W_d <= 4096.  Coiflet coefficients reach beyond their 2^L block, so their holograms
+ * come from wasabi_hologram only (a halo round each window, see there); wasabi_hologram_fused and
+ * the server take Haar LUTs.
  * ------------------------------------------------------------------------------------------- */
 typedef struct {
     double wavelength;   /* metres, 0 < wavelength < 2 pitch                                  */
@@ -105,6 +114,7 @@ typedef struct {
     int32_t phases;      /* 0: one table per plane (points snapped to the 2^L grid);
                             1: 4^L phase tables per plane (points snapped to the pixel grid);
                             n_depth 4^L <= 2^20                                                */
+    int32_t wavelet;     /* CGH_HAAR, or CGH_COIF1 (the coiflet of order 1, six taps)          */
 } wasabi_lut_params;
 
 typedef struct wasabi_lut wasabi_lut; /* opaque, library-owned, device-resident */
@@ -182,6 +192,10 @@ int wasabi_idwt(const void *psi_dev, int32_t nx, int32_t ny, int32_t levels, voi
 /* Large-scale procedure (Sec. 2, steps 2-4): the ny x nx hologram window at global (ox, oy),
  * computed as sub-holograms of at most sub x sub pixels (sub = 0: one sub-hologram), each by
  * wasabi_superpose into a scratch wavelet field followed by wasabi_idwt into its part of u.
+ * With a coiflet LUT each sub-hologram's window is grown by a halo of 5 2^L pixels on every side
+ * (the reach of the six-tap filters over L levels), superposed, inverted as a whole with the
+ * periodised synthesis filter bank, and only its centre written to u: exact for gamma >= 1,
+ * like Haar.
  *   u_dev : device, ny rows of nx complex64, row stride ld_u >= nx; overwritten.
  * Requires ox, oy, nx, ny and sub multiples of 2^L.  Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
 int wasabi_hologram(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t n, int64_t ox,
@@ -191,7 +205,8 @@ int wasabi_hologram(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t 
 /* Same result as wasabi_hologram, computed tile by tile: each tile's Haar blocks are superposed
  * (Eq.(2)) and inverted (Sec. 2, step 3) inside on-chip memory, so the wavelet field never goes
  * to device memory.  Exact reordering for Haar, whose 2^L x 2^L blocks are independent.
- * Same arguments and errors as wasabi_hologram without `sub`. */
+ * Same arguments and errors as wasabi_hologram without `sub`; a coiflet LUT gives CGH_EINVAL
+ * (its coefficients reach beyond the tile's blocks). */
 int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t n,
                           int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *u_dev,
                           int64_t ld_u, void *stream);
@@ -213,7 +228,8 @@ int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, in
  * recording plane z_wrp metres from it.  Every point's depth is taken from the WRP (z - z_wrp,
  * which must lie in the LUT's [z_min, z_max]; others contribute nothing), WASABI computes the
  * field on the WRP (as wasabi_quantize + wasabi_hologram_fused at origin (0, 0)), and
- * cgh_propagate carries it over z_wrp to the hologram plane, in place in u.
+ * cgh_propagate carries it over z_wrp to the hologram plane, in place in u (a coiflet LUT's WRP
+ * field comes from wasabi_hologram instead of the fused path).
  *   pts_dev : device, n x 4 double {x, y, z, a} metres (as for wasabi_quantize).
  *   u_dev   : device, ny x nx complex64 row-major, contiguous; overwritten.
  *   nx, ny  : powers of two in [64, 8192].

@@ -35,6 +35,7 @@ CGH_ENOTFOUND, CGH_ETIMEDOUT, CGH_ECANCELED = -5, -6, -7
 C64, C128 = 0, 1
 F32, F16, BF16 = 0, 1, 2
 FULL, CIRC = 0, 1
+HAAR, COIF1 = 0, 1
 
 
 class CghError(RuntimeError):
@@ -48,7 +49,7 @@ class _LutParams(ctypes.Structure):
                 ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
                 ("n_depth", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("max_window", ctypes.c_int32), ("value_dtype", ctypes.c_int32),
-                ("gamma", ctypes.c_double), ("phases", ctypes.c_int32)]
+                ("gamma", ctypes.c_double), ("phases", ctypes.c_int32), ("wavelet", ctypes.c_int32)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -198,11 +199,12 @@ class LutParams:
     gamma: float = 0.05
     value_dtype: int = F32
     phases: int = 0   # 1: 4^L phase tables per plane, points on any pixel
+    wavelet: int = HAAR  # COIF1: the coiflet of order 1 (holograms through wasabi_hologram)
 
     def c(self) -> _LutParams:
         return _LutParams(self.wavelength, self.pitch, self.z_min, self.z_max, self.n_depth,
                           self.levels, self.max_window, self.value_dtype, self.gamma,
-                          int(self.phases))
+                          int(self.phases), int(self.wavelet))
 
 
 class Lut:

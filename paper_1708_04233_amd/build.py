@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcgh.so")
-SOURCES = ["runtime.cpp", "server.cpp", "direct.hip", "lut.hip", "wasabi.hip", "propagate.hip"]
+SOURCES = ["runtime.cpp", "server.cpp", "direct.hip", "lut.hip", "wasabi.hip", "propagate.hip", "coiflet.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -164,6 +164,14 @@ namespace cgh {
 int lut_geometry(wasabi_lut *lut);
 int validate_params(const wasabi_lut_params *prm);
 
+// Analysis filter bank of `wavelet` (CGH_HAAR or CGH_COIF1) into lo/hi (8 entries each); returns taps.
+int wavelet_filters(int wavelet, double *lo, double *hi);
+
+// wasabi_hologram for a coiflet LUT: every sub-hologram grown by a halo, superposed, inverted with
+// the periodised synthesis filter bank, its centre copied to u (coiflet.hip).
+int coiflet_hologram(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox, int64_t oy,
+                     int32_t nx, int32_t ny, int32_t sub, void *u, int64_t ld_u, hipStream_t s);
+
 // Upper bound (bytes) of the device scratch wasabi_hologram_fused takes from the stream-ordered
 // pool for n points on an nx x ny window at origin (0, 0).
 int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny);

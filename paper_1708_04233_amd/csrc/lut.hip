@@ -178,6 +178,71 @@ __global__ __launch_bounds__(256) void psf_haar_kernel(int W, int nb, int sx, in
     }
 }
 
+// ---- coiflet tables: PSF in the pixel layout, periodised filter-bank transform, block order -----
+struct DwtFilters {
+    double lo[8], hi[8];
+    int taps;
+};
+
+// The W x W PSF table, disk centred on (W/2 + sx, W/2 + sy), row-major.
+__global__ __launch_bounds__(256) void psf_fill_kernel(int W, int sx, int sy, double z, double R2,
+                                                       double pitch, double lambda, double2 *T)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)W * W) return;
+    const int c = W / 2;
+    const double dr = (double)((int)(i / W) - c - sy), dq = (double)((int)(i % W) - c - sx);
+    double2 v = make_double2(0.0, 0.0);
+    if (dq * dq + dr * dr < R2) {
+        const double dist = sqrt((dq * pitch) * (dq * pitch) + (dr * pitch) * (dr * pitch) + z * z);
+        const double t = dist / lambda;  // revolutions; whole ones dropped below
+        double sn, cs;
+        sincospi(2.0 * (t - floor(t)), &sn, &cs);
+        v = make_double2(cs, sn);
+    }
+    T[i] = v;
+}
+
+// One periodised analysis step on every row (ROWS) or column of the top-left h x w region of a
+// W-wide table: a[k] = sum_t lo[t] x[(2k + t) mod len], d[k] = sum_t hi[t] x[(2k + t) mod len],
+// a into the first half of the line, d into the second.  One workgroup per line, staged in LDS.
+template <bool ROWS>
+__global__ __launch_bounds__(256) void dwt_line_kernel(double2 *T, int W, int h, int w, DwtFilters f)
+{
+    extern __shared__ double2 line[];
+    const int len = ROWS ? w : h, half = len / 2;
+    const int64_t base = ROWS ? (int64_t)blockIdx.x * W : (int64_t)blockIdx.x;
+    const int64_t step = ROWS ? 1 : W;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) line[i] = T[base + i * step];
+    __syncthreads();
+    for (int k = threadIdx.x; k < half; k += blockDim.x) {
+        double2 a = make_double2(0.0, 0.0), d = make_double2(0.0, 0.0);
+        for (int t = 0; t < f.taps; ++t) {
+            const double2 x = line[(2 * k + t) % len];
+            a.x += f.lo[t] * x.x;
+            a.y += f.lo[t] * x.y;
+            d.x += f.hi[t] * x.x;
+            d.y += f.hi[t] * x.y;
+        }
+        T[base + k * step] = a;
+        T[base + (half + k) * step] = d;
+    }
+}
+
+// Mallat-layout coefficients -> the block-major order of the selection (block (br, bc), code) and
+// their strength keys, as psf_haar_kernel writes them.
+__global__ __launch_bounds__(256) void mallat_to_blocks_kernel(const double2 *T, int W, int L, double2 *coef,
+                                                               uint32_t *magq)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)W * W) return;
+    const int BB = 1 << (2 * L), nb = W >> L;
+    const int64_t blk = i / BB;
+    const double2 v = T[block_to_flat((int)(blk / nb), (int)(blk % nb), (int)(i % BB), W, L)];
+    coef[i] = v;
+    magq[i] = __float_as_uint((float)(v.x * v.x + v.y * v.y));
+}
+
 // ---- block-wide exclusive scan of one flag per thread (1024 threads) --------------------------
 __device__ inline int block_excl_count(bool flag, int *wave_tot, int &total)
 {
@@ -706,12 +771,37 @@ extern "C" int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, 
     }
     const double lambda = prm->wavelength;
     std::vector<SelPlane> planes(n);
+    // coiflet tables are transformed in a pixel-layout buffer of the largest table first
+    double2 *tbuf = nullptr;
+    DwtFilters filt;
+    filt.taps = wavelet_filters(prm->wavelet, filt.lo, filt.hi);
+    if (prm->wavelet != CGH_HAAR) {
+        int64_t wmax = 0;
+        for (int d = 0; d < n; ++d) wmax = std::max<int64_t>(wmax, lut->W[d]);
+        if (hipMalloc((void **)&tbuf, sizeof(double2) * wmax * wmax) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(CGH_ENOMEM, "coiflet table buffer of %lld coefficients failed", (long long)(wmax * wmax));
+        }
+    }
     for (int d = 0; d < n && !rc; ++d) {
         const int W = lut->W[d], nb = W / lut->B;
         const int ph = d % lut->P, sx = ph % lut->B, sy = ph / lut->B;  // table shift (phase tables)
         const double R2 = lut->R[d] * lut->R[d];
         double2 *c = coef + coef_off[d];
         uint32_t *m2 = mag2 + coef_off[d];
+        if (prm->wavelet != CGH_HAAR) {
+            ProfScope prof("psf_dwt", s);
+            const int64_t cnt = (int64_t)W * W;
+            const unsigned g = (unsigned)((cnt + 255) / 256);
+            hipLaunchKernelGGL(psf_fill_kernel, dim3(g), dim3(256), 0, s, W, sx, sy, lut->z[d], R2, prm->pitch,
+                               lambda, tbuf);
+            for (int l = 0; l < L; ++l) {
+                const int h = W >> l, w = W >> l;
+                hipLaunchKernelGGL(dwt_line_kernel<true>, dim3(h), dim3(256), sizeof(double2) * w, s, tbuf, W, h, w, filt);
+                hipLaunchKernelGGL(dwt_line_kernel<false>, dim3(w), dim3(256), sizeof(double2) * h, s, tbuf, W, h, w, filt);
+            }
+            hipLaunchKernelGGL(mallat_to_blocks_kernel, dim3(g), dim3(256), 0, s, tbuf, W, L, c, m2);
+        } else
         switch (L) {
         case 1: launch_psf_haar<1>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
         case 2: launch_psf_haar<2>(W, nb, sx, sy, lut->z[d], R2, prm->pitch, lambda, c, m2, s); break;
@@ -756,6 +846,7 @@ extern "C" int wasabi_build_lut(const wasabi_lut_params *prm, wasabi_lut **out, 
     (void)hipFree(coef);
     (void)hipFree(mag2);
     (void)hipFree(planes_dev);
+    (void)hipFree(tbuf);
     if (!rc) {
         int64_t blk_total = lut->desc_host[n - 1].blkoff_base + (int64_t)lut->desc_host[n - 1].nb * lut->desc_host[n - 1].nb + 1;
         std::vector<int32_t> bo(blk_total);

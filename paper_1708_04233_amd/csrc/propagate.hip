@@ -210,6 +210,8 @@ extern "C" int wasabi_hologram_wrp(const wasabi_lut *lut, const double *pts, int
     wasabi_point *q = nullptr;
     if (n > 0 && (rc = sc.alloc((void **)&q, sizeof(wasabi_point) * (size_t)n))) return rc;
     if (n > 0 && (rc = quantize_shifted(lut, pts, n, z_wrp, q, s))) return rc;
-    if ((rc = wasabi_hologram_fused(lut, q, n, 0, 0, nx, ny, u, nx, s))) return rc;
+    rc = lut->prm.wavelet == CGH_HAAR ? wasabi_hologram_fused(lut, q, n, 0, 0, nx, ny, u, nx, s)
+                                      : wasabi_hologram(lut, q, n, 0, 0, nx, ny, 0, u, nx, s);
+    if (rc) return rc;
     return propagate_impl(u, u, nx, ny, z_wrp, lut->prm.pitch, lut->prm.wavelength, s);
 }

@@ -115,6 +115,7 @@ int validate_params(const wasabi_lut_params *prm)
         return fail(CGH_EINVAL, "unknown value_dtype");
     if (!(prm->gamma > 0) || !std::isfinite(prm->gamma)) return fail(CGH_EINVAL, "gamma must be > 0");
     if (prm->phases != 0 && prm->phases != 1) return fail(CGH_EINVAL, "phases must be 0 or 1");
+    if (prm->wavelet != CGH_HAAR && prm->wavelet != CGH_COIF1) return fail(CGH_EINVAL, "unknown wavelet");
     if (prm->phases && ((int64_t)prm->n_depth << (2 * prm->levels)) > (INT64_C(1) << 20))
         return fail(CGH_EINVAL, "n_depth * 4^L phase tables exceed 2^20");
     return CGH_OK;
@@ -146,11 +147,16 @@ int lut_geometry(wasabi_lut *lut)
         const double z = p.z_min + ((double)d + 0.5) * dz;
         const double R = z * tan_t / p.pitch;
         if (!(R < 1e6)) return fail(CGH_EINVAL, "plane %d: PSF radius too large", d);
-        const int64_t need = 2 * (int64_t)std::floor(R) + (p.phases ? q : 2);
+        // coiflet tables: a margin of 5 2^L pixels on each side keeps the disk's coefficients from
+        // wrapping round the periodised transform
+        const int64_t need = 2 * (int64_t)std::floor(R) + (p.phases ? q : 2) +
+                             (p.wavelet == CGH_COIF1 ? 2 * 5 * B : 0);
         const int64_t W = ((need + q - 1) / q) * q;
         if (W > p.max_window)
             return fail(CGH_EINVAL, "plane %d needs a %lld-pixel table > max_window %d", d,
                         (long long)W, p.max_window);
+        if (p.wavelet == CGH_COIF1 && W > 4096)
+            return fail(CGH_EINVAL, "plane %d: coiflet table side %lld > 4096", d, (long long)W);
         if (W / B > key_room)
             return fail(CGH_EINVAL, "plane %d: table side %lld too large for L=%d", d,
                         (long long)W, p.levels);
@@ -171,6 +177,25 @@ int lut_geometry(wasabi_lut *lut)
         }
     }
     return CGH_OK;
+}
+
+// Analysis filter bank of the LUT's wavelet: Haar (1, 1)/sqrt 2, or the coiflet of order 1 from its
+// closed form lo = sqrt(2)/32 (1-s, 5+s, 14+2s, 14-2s, 1-s, -3+s), s = sqrt 7 (Daubechies, Ten Lectures
+// on Wavelets, Sec. 8.2); hi[n] = (-1)^n lo[taps-1-n].  Returns the number of taps.
+int wavelet_filters(int wavelet, double *lo, double *hi)
+{
+    int taps;
+    if (wavelet == CGH_COIF1) {
+        const double s = std::sqrt(7.0), c = std::sqrt(2.0) / 32.0;
+        const double f[6] = {1 - s, 5 + s, 14 + 2 * s, 14 - 2 * s, 1 - s, -3 + s};
+        taps = 6;
+        for (int n = 0; n < taps; ++n) lo[n] = c * f[n];
+    } else {
+        taps = 2;
+        lo[0] = lo[1] = 1.0 / std::sqrt(2.0);
+    }
+    for (int n = 0; n < taps; ++n) hi[n] = ((n & 1) ? -1.0 : 1.0) * lo[taps - 1 - n];
+    return taps;
 }
 
 }  // namespace cgh

@@ -359,6 +359,8 @@ extern "C" int cgh_server_create(const cgh_server_config *cfg, cgh_server **out)
     if (cfg->max_slots < 1 || cfg->max_slots > 64) return fail(CGH_EINVAL, "max_slots must be 1..64");
     if (cfg->simulate && !(cfg->sim_ns_per_pixel >= 0)) return fail(CGH_EINVAL, "sim_ns_per_pixel must be >= 0");
     if (!cfg->simulate && !cfg->lut) return fail(CGH_EINVAL, "lut is NULL");
+    if (cfg->lut && cfg->lut->prm.wavelet != CGH_HAAR)
+        return fail(CGH_EINVAL, "the server computes jobs on the fused path, which needs a Haar LUT");
     std::unique_ptr<cgh_server> S(new cgh_server);
     S->cfg = *cfg;
     S->t0 = Clock::now();

@@ -1689,6 +1689,7 @@ int hologram_fused_shared(const wasabi_lut *lut, const wasabi_point *pts, int64_
 {
     int rc = check_common(lut, pts, n, 0, 0, nx, ny, u);
     if (rc) return rc;
+    if (lut->prm.wavelet != CGH_HAAR) return fail(CGH_EINVAL, "the fused path needs a Haar LUT");
     Scratch sc(s, arena, arena_bytes);
     return superpose_impl(lut, pts, n, 0, 0, nx, ny, u, nx, MODE_FUSED, s, false, &sc);
 }
@@ -1728,8 +1729,9 @@ extern "C" int wasabi_hologram(const wasabi_lut *lut, const wasabi_point *pts, i
     if (ld_u < nx) return fail(CGH_EINVAL, "ld_u < nx");
     const int B = lut->B;
     if (sub < 0 || sub % B) return fail(CGH_EINVAL, "sub must be 0 or a positive multiple of 2^L");
-    if (sub == 0) sub = std::max(nx, ny);
     hipStream_t s = (hipStream_t)stream;
+    if (lut->prm.wavelet != CGH_HAAR) return coiflet_hologram(lut, pts, n, ox, oy, nx, ny, sub, u, ld_u, s);
+    if (sub == 0) sub = std::max(nx, ny);
     if ((rc = prepare_pool())) return rc;
     const int32_t sx = std::min(sub, nx), sy = std::min(sub, ny);
     Scratch sc(s);
@@ -1767,5 +1769,7 @@ extern "C" int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *
     int rc = check_common(lut, pts, n, ox, oy, nx, ny, u);
     if (rc) return rc;
     if (ld_u < nx) return fail(CGH_EINVAL, "ld_u < nx");
+    if (lut->prm.wavelet != CGH_HAAR)
+        return fail(CGH_EINVAL, "the fused path inverts Haar blocks on chip; a coiflet LUT needs wasabi_hologram");
     return superpose_impl(lut, pts, n, ox, oy, nx, ny, u, ld_u, MODE_FUSED, (hipStream_t)stream);
 }

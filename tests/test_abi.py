@@ -29,7 +29,8 @@ def test_argument_validation_without_device():
     for bad in [dict(levels=0), dict(levels=7), dict(n_depth=0), dict(gamma=0.0),
                 dict(z_min=2e-3), dict(wavelength=3e-6), dict(value_dtype=5),
                 dict(max_window=512), dict(phases=2), dict(phases=1, n_depth=65536),
-                dict(phases=1, levels=5)]:   # phase tables: 2 * 496 + 64 > 1024
+                dict(phases=1, levels=5),    # phase tables: 2 * 496 + 64 > 1024
+                dict(wavelet=2), dict(wavelet=1, levels=5)]:   # coiflet: 2 * 496 + 2 + 320 > 1024
         prm = cgh.LutParams(**bad).c()
         assert lib.wasabi_build_lut(ctypes.byref(prm), ctypes.byref(h), None) == cgh.CGH_EINVAL, bad
         assert not h.value
