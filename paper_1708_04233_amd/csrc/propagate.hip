@@ -10,7 +10,8 @@
 //   3. per row of B: forward FFT along y, times H(fx, fy), inverse FFT along y;
 //   4. B transposed back into A;
 //   5. inverse FFT of every row of A into u'.
-// Every pass reads and writes the field once (16 B per pixel); twiddles and the transfer
+// Every pass reads and writes the field once (16 B per pixel); the row transforms go two radix-2
+// stages per barrier; twiddles and the transfer
 // function's phase come from FP64 angles (the phase reduced to revolutions first), rounded to FP32.
 #include <cmath>
 
@@ -43,19 +44,49 @@ __device__ inline float2 cmul(float2 a, float2 b)
 
 __device__ inline int bit_reverse(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
 
-// Radix-2 decimation-in-time FFT of buf[0, n) in LDS, input in bit-reversed order, output in natural
-// order.  INV: the conjugate twiddles (no 1/n).
+// Decimation-in-time FFT of buf[0, n) in LDS, input in bit-reversed order, output in natural order.
+// The radix-2 stages go two at a time: a thread loads the four points i0 + {0, h, 2h, 3h} of a
+// block of 4h, does the stage of span h and the stage of span 2h on them in registers and stores
+// them back, so there is one barrier and one LDS round trip per two stages; an odd last stage is
+// plain radix 2.  INV: the conjugate twiddles (no 1/n).
+template <bool INV>
+__device__ inline float2 twiddle(const float2 *tw, int k)
+{
+    float2 w = tw[k];
+    if (INV) w.y = -w.y;
+    return w;
+}
+
 template <bool INV>
 __device__ inline void fft_lds(float2 *buf, int n, int logn, const float2 *tw)
 {
-    for (int s = 1; s <= logn; ++s) {
-        const int h = 1 << (s - 1), stride = n >> s;  // exp(-2 pi i j / 2h) = tw[j * n / 2h]
+    int s = 1;
+    for (; s + 1 <= logn; s += 2) {
+        const int h = 1 << (s - 1);            // span of the first of the two stages
+        const int st1 = n >> s, st2 = n >> (s + 1);  // twiddle strides: W_2h^j = tw[j n / 2h]
+        for (int b = threadIdx.x; b < n / 4; b += blockDim.x) {
+            const int j = b & (h - 1);
+            const int i0 = ((b >> (s - 1)) << (s + 1)) + j;
+            const float2 w1 = twiddle<INV>(tw, j * st1);
+            const float2 w2 = twiddle<INV>(tw, j * st2), w3 = twiddle<INV>(tw, (j + h) * st2);
+            const float2 a0 = buf[i0], a1 = buf[i0 + h], a2 = buf[i0 + 2 * h], a3 = buf[i0 + 3 * h];
+            const float2 t1 = cmul(w1, a1), t3 = cmul(w1, a3);
+            const float2 b0 = make_float2(a0.x + t1.x, a0.y + t1.y), b1 = make_float2(a0.x - t1.x, a0.y - t1.y);
+            const float2 b2 = make_float2(a2.x + t3.x, a2.y + t3.y), b3 = make_float2(a2.x - t3.x, a2.y - t3.y);
+            const float2 u2 = cmul(w2, b2), u3 = cmul(w3, b3);
+            buf[i0] = make_float2(b0.x + u2.x, b0.y + u2.y);
+            buf[i0 + 2 * h] = make_float2(b0.x - u2.x, b0.y - u2.y);
+            buf[i0 + h] = make_float2(b1.x + u3.x, b1.y + u3.y);
+            buf[i0 + 3 * h] = make_float2(b1.x - u3.x, b1.y - u3.y);
+        }
+        __syncthreads();
+    }
+    if (s == logn) {  // one radix-2 stage left
+        const int h = 1 << (s - 1), stride = n >> s;
         for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
             const int j = b & (h - 1);
             const int i0 = ((b >> (s - 1)) << s) + j, i1 = i0 + h;
-            float2 w = tw[j * stride];
-            if (INV) w.y = -w.y;
-            const float2 a = buf[i0], t = cmul(w, buf[i1]);
+            const float2 a = buf[i0], t = cmul(twiddle<INV>(tw, j * stride), buf[i1]);
             buf[i0] = make_float2(a.x + t.x, a.y + t.y);
             buf[i1] = make_float2(a.x - t.x, a.y - t.y);
         }
