@@ -96,7 +96,15 @@ __device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, i
 }
 
 constexpr int kMaxLdsTiles = 4096;   // per-workgroup tile histograms live in LDS up to this
-constexpr int kDepthChunk = 8192;     // points per workgroup in the plane sort
+constexpr int kDepthChunk = 8192;     // most points per workgroup in the plane sort
+
+// Points per workgroup of the plane sort: 8192, or fewer for small point sets so that at least
+// ~64 workgroups share the work (multiples of the 1024-thread workgroup).
+inline int64_t depth_chunk(int64_t n)
+{
+    const int64_t c = ((n + 63) / 64 + 1023) / 1024 * 1024;
+    return std::min<int64_t>(std::max<int64_t>(c, 1024), kDepthChunk);
+}
 
 // ---- point sort by (plane, row band): points grouped by plane and, within a plane, by 64-row band
 //      (invalid ones last).  Tile lists built from this order walk each plane's points by row, so
@@ -119,7 +127,7 @@ __device__ inline int sort_key(const wasabi_point &p, const SortKey &k)
 
 template <bool LDS>
 __global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *pts, int64_t n,
-                                                           SortKey key, int32_t *counts)
+                                                           SortKey key, int64_t chunk, int32_t *counts)
 {
     extern __shared__ int hist[];  // nbins (LDS variant)
     const int nbins = key.n_tables * key.nyb + 1;
@@ -127,8 +135,8 @@ __global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *p
         for (int i = threadIdx.x; i < nbins; i += 1024) hist[i] = 0;
         __syncthreads();
     }
-    const int64_t j0 = (int64_t)blockIdx.x * kDepthChunk;
-    const int64_t j1 = min(n, j0 + kDepthChunk);
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    const int64_t j1 = min(n, j0 + chunk);
     for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
         const int d = sort_key(pts[j], key);
         if (LDS) atomicAdd(&hist[d], 1);
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *p
 
 template <bool LDS>
 __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point *pts, int64_t n,
-                                                             SortKey key,
+                                                             SortKey key, int64_t chunk,
                                                              unsigned long long *cursor,
                                                              wasabi_point *sorted)
 {
@@ -151,8 +159,8 @@ __global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point 
     const int nbins = key.n_tables * key.nyb + 1;
     int *cnt = sh;
     unsigned long long *base = (unsigned long long *)(sh + ((nbins + 1) & ~1));
-    const int64_t j0 = (int64_t)blockIdx.x * kDepthChunk;
-    const int64_t j1 = min(n, j0 + kDepthChunk);
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    const int64_t j1 = min(n, j0 + chunk);
     if (LDS) {
         for (int i = threadIdx.x; i < nbins; i += 1024) cnt[i] = 0;
         __syncthreads();
@@ -238,24 +246,28 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
             }
 }
 
-// Ordered lists: chunk w (64 consecutive sorted points) writes its per-tile counts to column w of a
+// Ordered lists: chunk w (`cpts` consecutive sorted points) writes its per-tile counts to column w of a
 // tile-major matrix; the exclusive scan of that matrix gives each chunk its slice of every tile's
 // list, in chunk order.  Inside a chunk one wave takes the points one after another (lanes spread
 // over the point's tiles), so every tile's list keeps the sorted point order exactly.
-constexpr int kChunk = 64;
+constexpr int kChunk = 64;      // threads per workgroup, and the most points per chunk
+
+// Points per chunk: 32 for small point sets (twice the workgroups, half the points each walks in
+// turn), else 64 (half the matrix).
+inline int chunk_pts(int64_t n) { return n <= 65536 ? 32 : kChunk; }
 
 __global__ __launch_bounds__(kChunk) void bin_count_matrix_kernel(const wasabi_point *pts, int64_t n,
                                                                   const DepthDesc *desc, int n_tables,
-                                                                  int L, TileGeom g, int nwg,
+                                                                  int L, TileGeom g, int nwg, int cpts,
                                                                   int32_t *mat)
 {
     __shared__ int hist[kMaxLdsTiles];
     const int ntiles = g.nlx * g.nly;
     for (int i = threadIdx.x; i < ntiles; i += kChunk) hist[i] = 0;
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * cpts + threadIdx.x;
     int ty0, ty1, tx0, tx1;
-    if (j < n && footprint(pts[j], desc, n_tables, L, g, ty0, ty1, tx0, tx1))
+    if (threadIdx.x < cpts && j < n && footprint(pts[j], desc, n_tables, L, g, ty0, ty1, tx0, tx1))
         for (int ty = ty0; ty < ty1; ++ty)
             for (int tx = tx0; tx < tx1; ++tx) atomicAdd(&hist[ty * g.nlx + tx], 1);
     __syncthreads();
@@ -264,7 +276,7 @@ __global__ __launch_bounds__(kChunk) void bin_count_matrix_kernel(const wasabi_p
 
 __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_point *pts, int64_t n,
                                                                  const DepthDesc *desc, int n_tables,
-                                                                 int L, TileGeom g, int nwg,
+                                                                 int L, TileGeom g, int nwg, int cpts,
                                                                  const int64_t *moff, int32_t *list)
 {
     // next free list position of this workgroup's segment in every tile's list (all loads in
@@ -273,8 +285,8 @@ __global__ __launch_bounds__(kChunk) void bin_fill_matrix_kernel(const wasabi_po
     __shared__ int fp[kChunk][4];
     const int ntiles = g.nlx * g.nly;
     for (int i = threadIdx.x; i < ntiles; i += kChunk) pos[i] = moff[(int64_t)i * nwg + blockIdx.x];
-    const int64_t j0 = (int64_t)blockIdx.x * kChunk;
-    const int np = (int)min((int64_t)kChunk, n - j0);
+    const int64_t j0 = (int64_t)blockIdx.x * cpts;
+    const int np = (int)min((int64_t)cpts, n - j0);
     {
         int ty0 = 0, ty1 = 0, tx0 = 0, tx1 = 0;
         if (threadIdx.x < np && !footprint(pts[j0 + threadIdx.x], desc, n_tables, L, g, ty0, ty1, tx0, tx1))
@@ -1375,7 +1387,7 @@ int64_t pair_bound(const wasabi_lut *lut, int64_t n, const TileGeom &g)
 
 bool use_matrix_path(int64_t n, int64_t ntiles)
 {
-    const int64_t nwg = (n + kChunk - 1) / kChunk;
+    const int64_t nwg = (n + chunk_pts(n) - 1) / chunk_pts(n);
     return n > 0 && ntiles <= kMaxLdsTiles && nwg * ntiles <= (INT64_C(1) << 24);
 }
 
@@ -1410,12 +1422,13 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     // plane sort
     CGH_TRY_HIP(hipMemsetAsync(dcounts, 0, sizeof(int32_t) * nbins, s));
     const bool lds_depth = nbins <= 4096;
-    const unsigned dgrid = (unsigned)std::max<int64_t>((n + kDepthChunk - 1) / kDepthChunk, 1);
+    const int64_t dchunk = depth_chunk(n);
+    const unsigned dgrid = (unsigned)std::max<int64_t>((n + dchunk - 1) / dchunk, 1);
     if (n > 0) {
         if (lds_depth)
-            hipLaunchKernelGGL(depth_count_kernel<true>, dim3(dgrid), dim3(1024), sizeof(int) * nbins, s, pts, n, key, dcounts);
+            hipLaunchKernelGGL(depth_count_kernel<true>, dim3(dgrid), dim3(1024), sizeof(int) * nbins, s, pts, n, key, dchunk, dcounts);
         else
-            hipLaunchKernelGGL(depth_count_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dcounts);
+            hipLaunchKernelGGL(depth_count_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dchunk, dcounts);
         CGH_CHECK_LAUNCH("depth_count_kernel");
     }
     if ((rc = scan_counts(dcounts, nbins, doff, sc, s))) return rc;
@@ -1423,13 +1436,13 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
         CGH_TRY_HIP(hipMemcpyAsync(dcursor, doff, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
         const size_t sh = sizeof(int) * ((nbins + 1) & ~1) + sizeof(unsigned long long) * nbins;
         if (lds_depth)
-            hipLaunchKernelGGL(depth_scatter_kernel<true>, dim3(dgrid), dim3(1024), sh, s, pts, n, key, dcursor, sorted);
+            hipLaunchKernelGGL(depth_scatter_kernel<true>, dim3(dgrid), dim3(1024), sh, s, pts, n, key, dchunk, dcursor, sorted);
         else
-            hipLaunchKernelGGL(depth_scatter_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dcursor, sorted);
+            hipLaunchKernelGGL(depth_scatter_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dchunk, dcursor, sorted);
         CGH_CHECK_LAUNCH("depth_scatter_kernel");
     }
     // tile lists over the sorted points
-    const int64_t nwg = (n + kChunk - 1) / kChunk;
+    const int64_t nwg = (n + chunk_pts(n) - 1) / chunk_pts(n);
     const unsigned pblocks = (unsigned)((n + 255) / 256);
     *ordered_out = false;
     if (use_matrix_path(n, ntiles)) {
@@ -1438,12 +1451,12 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
         int64_t *moff;
         if ((rc = sc.alloc((void **)&mat, sizeof(int32_t) * nwg * ntiles))) return rc;
         if ((rc = sc.alloc((void **)&moff, sizeof(int64_t) * (nwg * ntiles + 1)))) return rc;
-        hipLaunchKernelGGL(bin_count_matrix_kernel, dim3((unsigned)nwg), dim3(kChunk), 0, s, sorted, n, lut->desc, nd, L, g, (int)nwg, mat);
+        hipLaunchKernelGGL(bin_count_matrix_kernel, dim3((unsigned)nwg), dim3(kChunk), 0, s, sorted, n, lut->desc, nd, L, g, (int)nwg, chunk_pts(n), mat);
         CGH_CHECK_LAUNCH("bin_count_matrix_kernel");
         if ((rc = scan_counts(mat, nwg * ntiles, moff, sc, s))) return rc;
         hipLaunchKernelGGL(gather_tile_off_kernel, dim3((unsigned)((ntiles + 256) / 256)), dim3(256), 0, s, moff, ntiles, (int)nwg, off);
         CGH_CHECK_LAUNCH("gather_tile_off_kernel");
-        hipLaunchKernelGGL(bin_fill_matrix_kernel, dim3((unsigned)nwg), dim3(kChunk), 0, s, sorted, n, lut->desc, nd, L, g, (int)nwg, moff, list);
+        hipLaunchKernelGGL(bin_fill_matrix_kernel, dim3((unsigned)nwg), dim3(kChunk), 0, s, sorted, n, lut->desc, nd, L, g, (int)nwg, chunk_pts(n), moff, list);
         CGH_CHECK_LAUNCH("bin_fill_matrix_kernel");
     } else {
         CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
@@ -1686,7 +1699,7 @@ int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_
                 r(4 * nbins) + r(8 * (nbins + 1)) + r(8 * nbins) + r(16 * std::max<int64_t>(n, 1)) +
                 scan(nbins);
     if (use_matrix_path(n, ntiles)) {
-        const int64_t cells = (n + kChunk - 1) / kChunk * ntiles;
+        const int64_t cells = (n + chunk_pts(n) - 1) / chunk_pts(n) * ntiles;
         t += r(4 * cells) + r(8 * (cells + 1)) + scan(cells);
     } else {
         t += scan(ntiles);
