@@ -367,6 +367,27 @@ __global__ __launch_bounds__(1024) void scan_local_kernel(const int32_t *counts,
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
+// Exclusive scan of a short count array by one workgroup: off[i] for i < n, off[n] = the total,
+// and the same offsets into `copy` unless it is NULL.
+__global__ __launch_bounds__(1024) void scan_small_kernel(const int32_t *counts, int64_t n, int64_t *off,
+                                                          unsigned long long *copy)
+{
+    __shared__ int64_t ws[16];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < n; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < n ? counts[i] : 0;
+        int64_t tot;
+        const int64_t excl = carry + block_incl_scan(v, ws, tot) - v;
+        if (i < n) {
+            off[i] = excl;
+            if (copy) copy[i] = (unsigned long long)excl;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) off[n] = carry;
+}
+
 __global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t *bsum, int64_t nb, int64_t *total_out)
 {
     __shared__ int64_t ws[16];
@@ -1350,8 +1371,17 @@ int check_window(int L, int64_t ox, int64_t oy, int32_t nx, int32_t ny)
 }  // namespace
 
 // Exclusive scan of `count` int32 values into int64 offsets (count + 1 values) on stream s.
-int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc, hipStream_t s)
+// Exclusive scan of count int32 counts into count + 1 int64 offsets; short arrays (up to 16384) in
+// one workgroup, which also writes the offsets into `copy` when it is not NULL.
+int scan_counts_copy(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc, hipStream_t s,
+                     unsigned long long *copy)
 {
+    if (count <= 16384) {
+        hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(1024), 0, s, counts, count, off, copy);
+        CGH_CHECK_LAUNCH("scan_small_kernel");
+        return CGH_OK;
+    }
+    if (copy) return fail(CGH_EINVAL, "scan copy needs at most 16384 counts");
     const int64_t nblk = (count + 1023) / 1024;
     int64_t *bsum;
     int rc = sc.alloc((void **)&bsum, sizeof(int64_t) * nblk);
@@ -1363,6 +1393,11 @@ int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc,
     hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, off, count, bsum);
     CGH_CHECK_LAUNCH("scan_add_kernel");
     return CGH_OK;
+}
+
+int scan_counts(const int32_t *counts, int64_t count, int64_t *off, Scratch &sc, hipStream_t s)
+{
+    return scan_counts_copy(counts, count, off, sc, s, nullptr);
 }
 
 namespace {
@@ -1431,9 +1466,12 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
             hipLaunchKernelGGL(depth_count_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dchunk, dcounts);
         CGH_CHECK_LAUNCH("depth_count_kernel");
     }
-    if ((rc = scan_counts(dcounts, nbins, doff, sc, s))) return rc;
+    // the scatter's cursors start at the offsets: written by the scan for short bin arrays
+    const bool small_bins = nbins <= 16384;
+    if ((rc = scan_counts_copy(dcounts, nbins, doff, sc, s, small_bins ? dcursor : nullptr))) return rc;
     if (n > 0) {
-        CGH_TRY_HIP(hipMemcpyAsync(dcursor, doff, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
+        if (!small_bins)
+            CGH_TRY_HIP(hipMemcpyAsync(dcursor, doff, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
         const size_t sh = sizeof(int) * ((nbins + 1) & ~1) + sizeof(unsigned long long) * nbins;
         if (lds_depth)
             hipLaunchKernelGGL(depth_scatter_kernel<true>, dim3(dgrid), dim3(1024), sh, s, pts, n, key, dchunk, dcursor, sorted);
