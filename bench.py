@@ -120,7 +120,7 @@ def counter_traffic(workload, kernel, launches=1):
 
 
 def image_psnr(torch, cgh, u, ref, depths):
-    """Image-domain PSNR (the paper judges holograms by their reconstructions): both complex64
+    """Image-domain PSNR (the paper assesses holograms by their reconstructions): both complex64
     holograms on the GPU are propagated back by -z for each depth z (angular spectrum) and their
     intensities compared, 10 log10(max I_ref^2 / mean (I - I_ref)^2), pooled over the depths."""
     num = den = peak = 0.0

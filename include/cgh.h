@@ -212,7 +212,7 @@ int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, in
                           int64_t ld_u, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
- * Numerical propagation (the reconstruction Sec. 3 judges holograms by) and the wavefront
+ * Numerical propagation (the reconstruction Sec. 3 assesses holograms by) and the wavefront
  * recording plane (the conclusion's next step).
  *
  * cgh_propagate: angular-spectrum propagation of a complex field by `distance` metres (either

@@ -1,5 +1,5 @@
 // Angular-spectrum propagation of a sampled complex field (the numerical reconstruction the paper
-// judges holograms by, Sec. 3) and the hologram through a wavefront recording plane (the method the
+// assesses holograms by, Sec. 3) and the hologram through a wavefront recording plane (the method the
 // conclusion names as the next step) for gfx950.
 //
 // u' = IFFT2(FFT2(u) H), H(fx, fy) = exp(i 2 pi d sqrt(1/lambda^2 - fx^2 - fy^2)) on the propagating
