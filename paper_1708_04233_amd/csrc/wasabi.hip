@@ -943,6 +943,10 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, double unsca
         }
         __syncthreads();
     }
+    // The pixels are written with non-temporal stores: the hologram is not read again here, and
+    // streaming it past the caches keeps the table entries there (65536^2, gamma 0.02: 14.3 -> 12.6 ms).
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef float v2f __attribute__((ext_vector_type(2)));
     const bool wide = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)ld * sizeof(float2)) & 15) == 0;
     for (int qi = threadIdx.x; qi < QT * QT; qi += NT) {
         const int qm = qi / QT, qn = qi % QT;           // quad row / column in the tile
@@ -958,10 +962,10 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, double unsca
         for (int i = 0; i < 2; ++i) {
             const float2 p0 = haar_up(S1, H, V, D, i, 0), p1 = haar_up(S1, H, V, D, i, 1);
             if (wide) {
-                *reinterpret_cast<float4 *>(o + i * ld) = make_float4(p0.x, p0.y, p1.x, p1.y);
+                __builtin_nontemporal_store((v4f){p0.x, p0.y, p1.x, p1.y}, reinterpret_cast<v4f *>(o + i * ld));
             } else {
-                o[i * ld] = p0;
-                o[i * ld + 1] = p1;
+                __builtin_nontemporal_store((v2f){p0.x, p0.y}, reinterpret_cast<v2f *>(o + i * ld));
+                __builtin_nontemporal_store((v2f){p1.x, p1.y}, reinterpret_cast<v2f *>(o + i * ld + 1));
             }
         }
     }
