@@ -138,6 +138,25 @@ def psnr(u, ref):
     return float("inf") if mse == 0 else 10 * np.log10(float(np.max(np.abs(ref)) ** 2) / mse)
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: a device-to-device copy of nbytes (each byte read and written once),
+    best of reps, timed with events on torch's stream, where the copy runs."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (best * 1e-3) / 1e9, 1)
+
+
 def timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -279,6 +298,21 @@ def main():
     ref = cgh.cgh_direct(snapped_t, nx, ny, window=cgh.CIRC, out_dtype=torch.complex128).cpu().numpy()
     p40, p05 = psnr(u40, ref), psnr(u05, ref)
     log("psnr gamma40 %.2f dB, gamma 0.05 %.2f dB; direct %.3f ms" % (p40, p05, ms_direct))
+    # the same selectivity with the LUT values stored in FP16 (FP32 accumulation, FP64 table phase)
+    lut_f16 = None
+    if args.lut == "f32":
+        l16 = cgh.wasabi_build_lut(cgh.LutParams(n_depth=w["n_depth"], levels=L, gamma=g40,
+                                                 max_window=w["max_window"], value_dtype=cgh.F16))
+        ms16 = timed(lambda: step(l16), args.steps, 2, torch)
+        step(l16)
+        torch.cuda.synchronize()
+        u16 = u.cpu().numpy().astype(np.complex128)
+        lut_f16 = {"ms_per_step": round(ms16, 4), "value": round(mpp / (ms16 * 1e-3), 1),
+                   "psnr_db": round(psnr(u16, ref), 2),
+                   "rel_l2_vs_f32_lut": float(np.linalg.norm(u16 - u40) / np.linalg.norm(u40)),
+                   "speedup_vs_direct": round(ms_direct / ms16, 3)}
+        del l16
+        log("f16 LUT: %.3f ms/step, psnr %.2f dB" % (ms16, lut_f16["psnr_db"]))
     # image-domain PSNR: reconstructions at three depths of the scene
     rec_depths = (0.3e-3, 0.8e-3, 1.3e-3)
     u40_t = torch.from_numpy(u40.astype(np.complex64)).cuda()
@@ -302,7 +336,7 @@ def main():
                 "traffic": traffic, "algorithmic_bytes": algo_bytes,
                 "scatter_adds": scatter, "scatter_adds_per_s": round(scatter / t_tile, 1),
                 "lut_stream_GBps": round(scatter * (10 if args.lut == "f32" else 6) / t_tile / 1e9, 1),
-                "ms_per_launch": round(kernels["tile_fused"], 4)}
+                "ms_per_launch": round(kernels["tile_fused"], 4), "copy_GBps": copy_bandwidth(torch)}
 
     # ---- CPU baseline: the oracle on the same hologram ---------------------------------------
     cpu = None
@@ -342,6 +376,7 @@ def main():
         "direct": {"value": round(mpp / (ms_direct * 1e-3), 1), "ms_per_step": round(ms_direct, 4),
                    "window": "circ", "dtype": "f32 sums, f64 phase", "psnr_db": "inf"},
         "speedup_vs_direct": round(ms_direct / ms_step, 3),
+        "lut_f16": lut_f16,
         "workload_gamma": {"gamma": w["gamma"], "psnr_db": round(p05, 2), "image_psnr_db": round(img05, 2),
                            "value": round(mpp / (ms_g05 * 1e-3), 1), "ms_per_step": round(ms_g05, 4),
                            "lut_build_ms": round(build05_ms, 1)},
@@ -379,8 +414,13 @@ def run_large(args, torch, cgh):
     wins = [(int(v[0]) * B, int(v[1]) * B) for v in rng.integers(0, (nx - 1024) // B, (4, 2))]
     results = {}
     direct_ref = {}
-    for g in (w["gamma"], g40):
-        prm = cgh.LutParams(n_depth=w["n_depth"], levels=L, gamma=g, max_window=w["max_window"], value_dtype=vt)
+    # the workload's gamma and the 40 dB gamma; at 65536^2 also the 40 dB gamma with FP16 LUT values
+    runs = [(w["gamma"], vt, ""), (g40, vt, "")]
+    if big and args.lut == "f32":
+        runs.append((g40, cgh.F16, "_f16"))
+    for g, vt_run, tag in runs:
+        prm = cgh.LutParams(n_depth=w["n_depth"], levels=L, gamma=g, max_window=w["max_window"],
+                            value_dtype=vt_run)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lut = cgh.wasabi_build_lut(prm)
@@ -432,13 +472,13 @@ def run_large(args, torch, cgh):
                "lut_entries": int(info["total_entries"]), "kernels_ms": kern}
         t_tile = kern.get("tile_fused", ms) * 1e-3
         algo = 8 * nx * ny + int(info["device_bytes"]) + 16 * n
-        symbol = "%s<%d, %d, 1>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt)
+        symbol = "%s<%d, %d, 1>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt_run)
         res["roofline"] = {"kernel": "tile_fused", "symbol": symbol, "bound": "hbm",
                            "achieved": round(algo / t_tile / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(algo / t_tile / 1e9 / HBM_PEAK_GBS, 4),
                            "traffic": counter_traffic("%s@%.2f" % (w["name"], g), symbol),
                            "algorithmic_bytes": algo}
-        if g == w["gamma"]:
+        if g == w["gamma"] and not tag:
             # the paper's procedure: sub-holograms (8192^2 for the 65536^2 case) superposed into a
             # wavelet field and inverted into their part of the hologram
             sub = 8192 if big else 4096
@@ -468,17 +508,19 @@ def run_large(args, torch, cgh):
                                   "traffic_all_launches": counter_traffic("%s@%.2f-sub%d" % (w["name"], g, sub),
                                                                           "idwt_kernel<%d>" % L, sk["idwt"][1]),
                                   "algorithmic_bytes": 16 * nx * ny},
-                "superpose_roofline": {"symbol": "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt),
+                "superpose_roofline": {"symbol": "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt_run),
                                        "bound": "hbm",
                                        "achieved": round(algo / (sup_ms * 1e-3) / 1e9, 1),
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": round(algo / (sup_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                        "traffic_all_launches": counter_traffic(
                                            "%s@%.2f-sub%d" % (w["name"], g, sub),
-                                           "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt),
+                                           "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt_run),
                                            sk["tile_superpose"][1]),
                                        "algorithmic_bytes": algo}}
-        results["gamma_%.2f" % g] = res
+        if tag:
+            res["lut_values"] = "f16"
+        results["gamma_%.2f%s" % (g, tag)] = res
         log(args.workload, res)
         del lut
     # direct sum of the whole hologram (circ window), FP32 output
@@ -498,6 +540,9 @@ def run_large(args, torch, cgh):
            "results": results,
            "direct": {"ms": round(ms_direct, 2), "value": round(mpp / (ms_direct * 1e-3), 1), "window": "circ"},
            "speedup_vs_direct_at_40db_gamma": round(ms_direct / main["ms_per_step"], 3),
+           "speedup_vs_direct_at_40db_gamma_f16_lut": (round(ms_direct / results["gamma_%.2f_f16" % g40]["ms_per_step"], 3)
+                                                       if "gamma_%.2f_f16" % g40 in results else None),
+           "hbm_copy_GBps": copy_bandwidth(torch),
            "paper_context": "paper: ~354 s for a 65536^2 hologram of 95,949 points on one CPU"}
     print(json.dumps(out), flush=True)
 
