@@ -140,3 +140,33 @@ def test_16384_storage_precision_vs_fp64(fp64_windows, dtype):
     err = float(np.sqrt(num / den))
     print("16384^2 %s LUT: relative L2 error vs FP64 oracle on 8 x 2048^2 windows = %.3e" % (dtype, err))
     assert err <= PREC_BOUND[dtype]
+
+
+def _gamma40():
+    """The 40 dB selectivity of the 2048^2 workload, written by the oracle's gamma sweep."""
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "gamma40_2048.txt")) as f:
+        return float([ln for ln in f if ln.strip() and not ln.startswith("#")][0])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_65536_40db_selectivity_windows(orc, dtype):
+    """65536^2 at the 40 dB selectivity (gamma >= 0.35: the dense-layout kernel), with FP32 and FP16
+    LUT values as the benchmark times it, on sampled windows against the oracle given the same
+    (storage-rounded) LUT values."""
+    w = WASABI_65536
+    g = _gamma40()
+    assert g >= 0.35
+    vt = {"f32": (orc.F32, cgh.F32), "f16": (orc.F16, cgh.F16)}[dtype]
+    kw = dict(n_depth=w["n_depth"], levels=w["levels"], gamma=g, max_window=w["max_window"])
+    olut = orc.build_lut(orc.LutParams(value_dtype=vt[0], **kw))
+    lut = cgh.wasabi_lut_import(cgh.LutParams(value_dtype=vt[1], **kw), olut.off, olut.idx, olut.val)
+    B = 1 << w["levels"]
+    pts = height_field_points(w["seed"], w["n"], w["nx"], B, w["z_lo"], w["z_hi"])
+    q = cgh.wasabi_quantize(lut, torch.from_numpy(pts).cuda())
+    u = torch.empty((w["ny"], w["nx"]), dtype=torch.complex64, device="cuda")
+    cgh.wasabi_hologram_fused(lut, q, 0, 0, w["nx"], w["ny"], u=u)
+    torch.cuda.synchronize()
+    check_windows(orc, olut, orc.quantize(pts, olut.params), u, w["nx"], B, seed=8, k=1)
+    del u
+    torch.cuda.empty_cache()
