@@ -785,76 +785,79 @@ __device__ inline void add_pair(unsigned long long *acc, const void *values, con
 // Walks a batch of (tile, point) pairs (lane k holds pair k's metadata) for L >= 3 (at most 8
 // block rows per pair).  The row ranges of all pairs of the batch are loaded at once, so a pair
 // waits only for its own entries; a pair's rows are walked as one flat range of entries (row r
-// owns [ex_r, ex_r + count_r)), 64 lanes x 2 entries per step, all loads of a step issued before
-// its adds.  Lanes past the end of a range re-read its last entry and add 0 to a word of their own.
-template <int L, int VT>
+// owns [ex_r, ex_r + count_r)), 64 lanes x 2 entries per step with all loads of a step issued
+// before its adds, and a last step of one entry per lane when at most 64 entries are left.
+// The kernel is bound by VALU issue here, so the per-entry work is kept small: entries are
+// addressed by 32-bit offsets from the pair's plane (the 16-bit keys keep a table side below
+// 8192 pixels, so a table holds fewer than 2^26 entries), and
+// lanes past the end are masked off rather than given neutral values.
+template <int L>
 struct PairStep {
     using S = TileShape<L>;
     int ex[S::TB], off[S::TB];
-    int total, eb, dst0;
+    int total, dst0;
+    const char *vals;       // the plane's first stored value
+    const uint16_t *keys;   // and key
     double sa;
-    float2 v[2];
-    int key[2], drow[2];
 };
 
 template <int L, int VT>
-__device__ inline void pair_setup(PairStep<L, VT> &P, int k, int cnt, const int *m_rs, const int *m_rc,
-                                  int m_eb, int m_dst0, float m_amp, int shift)
+__device__ inline void pair_setup(PairStep<L> &P, int k, const int *m_rs, const int *m_rc, int m_eb,
+                                  int m_dst0, float m_amp, int shift, const TileArgs &a)
 {
     using S = TileShape<L>;
+    constexpr int vbytes = VT == CGH_F32 ? 8 : 4;
     P.total = 0;
-    if (k < cnt) {
 #pragma unroll
-        for (int r = 0; r < S::TB; ++r) {
-            P.ex[r] = P.total;
-            P.off[r] = __builtin_amdgcn_readlane(m_rs[r], k) - P.total;
-            P.total += __builtin_amdgcn_readlane(m_rc[r], k);
+    for (int r = 0; r < S::TB; ++r) {
+        P.ex[r] = P.total;
+        P.off[r] = __builtin_amdgcn_readlane(m_rs[r], k) - P.total;
+        P.total += __builtin_amdgcn_readlane(m_rc[r], k);
+    }
+    const int eb = __builtin_amdgcn_readlane(m_eb, k);
+    P.vals = (const char *)a.values + (int64_t)eb * vbytes;
+    P.keys = a.keys + eb;
+    P.dst0 = __builtin_amdgcn_readlane(m_dst0, k);
+    P.sa = ldexp((double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k)), shift);
+}
+
+// The row of entry e: a select chain over rows R, R + 1, ... (indices fixed at compile time, so
+// that the rows' values stay in registers rather than in an indexed private array).
+template <int L, int R>
+__device__ inline void row_select(const PairStep<L> &P, int e, int &o, int &drow)
+{
+    if constexpr (R < TileShape<L>::TB) {
+        if (e >= P.ex[R]) {
+            o = P.off[R];
+            drow = R * TileShape<L>::ROW;
         }
-        P.eb = __builtin_amdgcn_readlane(m_eb, k);
-        P.dst0 = __builtin_amdgcn_readlane(m_dst0, k);
-        P.sa = ldexp((double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k)), shift);
+        row_select<L, R + 1>(P, e, o, drow);
+    }
+}
+
+// Entry e of the pair (0 <= e < total): its stored value, and its LDS word.
+template <int L, int VT>
+__device__ inline void pair_entry(const PairStep<L> &P, int e, float2 &v, int &word)
+{
+    using S = TileShape<L>;
+    int o = P.off[0], drow = 0;
+    row_select<L, 1>(P, e, o, drow);
+    const uint32_t rel = (uint32_t)(e + o);  // entry index within the plane's table
+    if constexpr (VT == CGH_F32) {
+        v = *reinterpret_cast<const float2 *>(P.vals + (rel << 3));
     } else {
-#pragma unroll
-        for (int r = 0; r < S::TB; ++r) P.ex[r] = P.off[r] = 0;
-        P.eb = 0;
-        P.dst0 = 0;
-        P.sa = 0.0;
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(P.vals + (rel << 2));
+        if constexpr (VT == CGH_F16) {
+            _Float16 lo, hi;
+            const uint16_t l16 = (uint16_t)(w & 0xffff), h16 = (uint16_t)(w >> 16);
+            __builtin_memcpy(&lo, &l16, 2);
+            __builtin_memcpy(&hi, &h16, 2);
+            v = make_float2((float)lo, (float)hi);
+        } else {
+            v = make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+        }
     }
-}
-
-template <int L, int VT>
-__device__ inline void pair_load(PairStep<L, VT> &P, int c, const void *values, const uint16_t *keys)
-{
-    using S = TileShape<L>;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int e = max(min(c + 64 * u + lane, P.total - 1), 0);
-        int o = P.off[0];
-        P.drow[u] = 0;
-#pragma unroll
-        for (int r = 1; r < S::TB; ++r)
-            if (e >= P.ex[r]) {
-                o = P.off[r];
-                P.drow[u] = r * S::ROW;
-            }
-        const int64_t idx = (int64_t)P.eb + e + o;
-        P.v[u] = load_value<VT>(values, idx);
-        P.key[u] = keys[idx];
-    }
-}
-
-template <int L, int VT>
-__device__ inline void pair_add(unsigned long long *acc, const PairStep<L, VT> &P, int c)
-{
-    using S = TileShape<L>;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const bool on = c + 64 * u + lane < P.total;
-        const int at = on ? P.dst0 + P.drow[u] + P.key[u] : lane;
-        atomicAdd(&acc[at], packed_fixed(P.v[u], on ? P.sa : 0.0));
-    }
+    word = P.dst0 + drow + *reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(P.keys) + (rel << 1));
 }
 
 template <int L, int VT>
@@ -863,6 +866,7 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
                                   float m_amp, int shift)
 {
     using S = TileShape<L>;
+    const int lane = threadIdx.x & 63;
     // all loads issued together: rows past the pair's last re-read its first row, counted as empty
     int m_rs[S::TB], m_rc[S::TB];
 #pragma unroll
@@ -871,18 +875,35 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
         m_rs[r] = row[m_bc0];
         m_rc[r] = row[m_bc1];
     }
+    int m_tot = 0;
 #pragma unroll
-    for (int r = 0; r < S::TB; ++r) m_rc[r] = r < m_nrows ? m_rc[r] - m_rs[r] : 0;
+    for (int r = 0; r < S::TB; ++r) {
+        m_rc[r] = r < m_nrows ? m_rc[r] - m_rs[r] : 0;
+        m_tot += m_rc[r];
+    }
+    // the pairs with at least one entry, in order
     auto next_pair = [&](int k) {
-        while (k < cnt && __builtin_amdgcn_readlane(m_nrows, k) == 0) ++k;
+        while (k < cnt && __builtin_amdgcn_readlane(m_tot, k) == 0) ++k;
         return k;
     };
     for (int k = next_pair(0); k < cnt; k = next_pair(k + 1)) {
-        PairStep<L, VT> A;
-        pair_setup(A, k, cnt, m_rs, m_rc, m_eb, m_dst0, m_amp, shift);
-        for (int c = 0; c < A.total; c += 128) {
-            pair_load(A, c, a.values, a.keys);
-            pair_add(acc, A, c);
+        PairStep<L> P;
+        pair_setup<L, VT>(P, k, m_rs, m_rc, m_eb, m_dst0, m_amp, shift, a);
+        int c = 0;
+        for (; P.total - c > 64; c += 128) {
+            const int e0 = c + lane, e1 = e0 + 64;  // e0 < total
+            float2 v0, v1;
+            int w0, w1;
+            pair_entry<L, VT>(P, e0, v0, w0);
+            if (e1 < P.total) pair_entry<L, VT>(P, e1, v1, w1);
+            atomicAdd(&acc[w0], packed_fixed(v0, P.sa));
+            if (e1 < P.total) atomicAdd(&acc[w1], packed_fixed(v1, P.sa));
+        }
+        if (c + lane < P.total) {
+            float2 v0;
+            int w0;
+            pair_entry<L, VT>(P, c + lane, v0, w0);
+            atomicAdd(&acc[w0], packed_fixed(v0, P.sa));
         }
     }
 }
