@@ -908,12 +908,14 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
     }
 }
 
-// One fixed-point word of the tile as FP32 (re, im).
-__device__ inline float2 fixed_value(unsigned long long w, double unscale)
+// One fixed-point word of the tile as FP32 (re, im), scaled by 2^e2 (e2 = -shift).  In FP32: the
+// integer is rounded once to 24 bits and then scaled exactly, which is the same rounding as
+// scaling in FP64 and converting (for results above the FP32 normal range's floor).
+__device__ inline float2 fixed_value(unsigned long long w, int e2)
 {
-    int re, im;
-    unpack_fixed(w, re, im);
-    return make_float2((float)((double)re * unscale), (float)((double)im * unscale));
+    const unsigned lo = (unsigned)w, hi = (unsigned)(w >> 32);
+    const int im = (int)lo, re = (int)(hi - (unsigned)(im >> 31));  // see unpack_fixed
+    return make_float2(ldexpf((float)re, e2), ldexpf((float)im, e2));
 }
 
 // One 2D inverse Haar step for one output of a quadruple: the output at row parity a, column parity
@@ -933,7 +935,7 @@ __device__ inline float2 haar_up(float2 s, float2 h, float2 v, float2 d, int a, 
 // position, i.e. a 2 x 2 pixel quad, and the threads of a wave take consecutive quads of a row, so
 // each store instruction writes whole rows of the tile.
 template <int L, int NT>
-__device__ inline void fixed_inverse_store(unsigned long long *acc, double unscale, float2 *out,
+__device__ inline void fixed_inverse_store(unsigned long long *acc, int e2, float2 *out,
                                            int64_t ld, int ty, int tx, int th, int tw)
 {
     using S = TileShape<L>;
@@ -942,7 +944,7 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, double unsca
     auto word = [](int blk, int m, int n) { return (blk / S::TB) * S::ROW + (blk % S::TB) * S::BS + m * B + n; };
     for (int i = threadIdx.x; i < QT * QT; i += NT) {
         const int at = word(i / (H1 * H1), (i % (H1 * H1)) / H1, i % H1);
-        f[at] = fixed_value(acc[at], unscale);
+        f[at] = fixed_value(acc[at], e2);
     }
     __syncthreads();
 #pragma unroll
@@ -986,9 +988,9 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, double unsca
         if (br >= (th >> L) || bc >= (tw >> L)) continue;
         const int blk = br * S::TB + bc;
         const float2 S1 = f[word(blk, m, n)];
-        const float2 H = fixed_value(acc[word(blk, m, H1 + n)], unscale);
-        const float2 V = fixed_value(acc[word(blk, H1 + m, n)], unscale);
-        const float2 D = fixed_value(acc[word(blk, H1 + m, H1 + n)], unscale);
+        const float2 H = fixed_value(acc[word(blk, m, H1 + n)], e2);
+        const float2 V = fixed_value(acc[word(blk, H1 + m, n)], e2);
+        const float2 D = fixed_value(acc[word(blk, H1 + m, H1 + n)], e2);
         float2 *o = out + ((int64_t)ty * kT + 2 * qm) * ld + (int64_t)tx * kT + 2 * qn;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -1005,7 +1007,7 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, double unsca
 
 // The tile's coefficients from its fixed-point words straight into the window's Mallat layout.
 template <int L, int NT>
-__device__ inline void fixed_mallat_store(const unsigned long long *acc, double unscale, float2 *field,
+__device__ inline void fixed_mallat_store(const unsigned long long *acc, int e2, float2 *field,
                                           const TileGeom &g, int ty, int tx, int th, int tw, bool nt)
 {
     using S = TileShape<L>;
@@ -1022,7 +1024,7 @@ __device__ inline void fixed_mallat_store(const unsigned long long *acc, double 
                 if (m >= hb || n >= wb) continue;
                 const int code = (((band & 2) ? h : 0) + (m & (h - 1))) * S::B + ((band & 1) ? h : 0) + (n & (h - 1));
                 put2(field + (row0 + (int64_t)ty * wf + m) * nx + col0 + (int64_t)tx * wf + n,
-                     fixed_value(acc[(m / h) * S::ROW + (n / h) * S::BS + code], unscale), nt);
+                     fixed_value(acc[(m / h) * S::ROW + (n / h) * S::BS + code], e2), nt);
             }
         }
     }
@@ -1031,7 +1033,7 @@ __device__ inline void fixed_mallat_store(const unsigned long long *acc, double 
     for (int i = threadIdx.x; i < wf * wf; i += NT) {
         const int m = i / wf, n = i % wf;
         if (m >= hb || n >= wb) continue;
-        put2(field + ((int64_t)ty * wf + m) * nx + (int64_t)tx * wf + n, fixed_value(acc[m * S::ROW + n * S::BS], unscale),
+        put2(field + ((int64_t)ty * wf + m) * nx + (int64_t)tx * wf + n, fixed_value(acc[m * S::ROW + n * S::BS], e2),
              nt);
     }
 }
@@ -1130,11 +1132,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
     }
     __syncthreads();
 
-    const double unscale = ldexp(1.0, -shift);
+    const int e2 = -shift;  // the words hold value * 2^shift
     if constexpr (MODE == MODE_PSI)
-        fixed_mallat_store<L, kTileThreads>(acc, unscale, a.out, a.g, ty, tx, th, tw, a.stream_psi != 0);
+        fixed_mallat_store<L, kTileThreads>(acc, e2, a.out, a.g, ty, tx, th, tw, a.stream_psi != 0);
     else
-        fixed_inverse_store<L, kTileThreads>(acc, unscale, a.out, a.ld, ty, tx, th, tw);
+        fixed_inverse_store<L, kTileThreads>(acc, e2, a.out, a.ld, ty, tx, th, tw);
 }
 
 // Dense-layout superposition.  Wave w of the tile's 8 waves owns the 512 coefficients
