@@ -690,7 +690,9 @@ __device__ inline int to_fixed(float v, double scaled_amp)
 __device__ inline unsigned long long packed_fixed(float2 v, double scaled_amp)
 {
     const int re = to_fixed(v.x, scaled_amp), im = to_fixed(v.y, scaled_amp);
-    return ((unsigned long long)(unsigned)re << 32) + (unsigned long long)(long long)im;
+    // re * 2^32 + im (im sign-extended): the high word is re - 1 when im < 0
+    const unsigned hi = (unsigned)re + (unsigned)(im >> 31);
+    return ((unsigned long long)hi << 32) | (unsigned)im;
 }
 
 __device__ inline void unpack_fixed(unsigned long long w, int &re, int &im)
@@ -795,14 +797,14 @@ template <int L>
 struct PairStep {
     using S = TileShape<L>;
     int ex[S::TB], off[S::TB];
-    int total, dst0;
+    int total, dst0b;       // dst0b: the LDS byte address of the pair's word 0
     const char *vals;       // the plane's first stored value
     const uint16_t *keys;   // and key
     double sa;
 };
 
 template <int L, int VT>
-__device__ inline void pair_setup(PairStep<L> &P, int k, const int *m_rs, const int *m_rc, int m_eb,
+__device__ inline void pair_setup(PairStep<L> &P, int k, const int *m_rs, const int *m_rcp, int m_eb,
                                   int m_dst0, float m_amp, int shift, const TileArgs &a)
 {
     using S = TileShape<L>;
@@ -810,38 +812,39 @@ __device__ inline void pair_setup(PairStep<L> &P, int k, const int *m_rs, const 
     P.total = 0;
 #pragma unroll
     for (int r = 0; r < S::TB; ++r) {
+        const unsigned rcp = (unsigned)__builtin_amdgcn_readlane(m_rcp[r / 2], k);
         P.ex[r] = P.total;
         P.off[r] = __builtin_amdgcn_readlane(m_rs[r], k) - P.total;
-        P.total += __builtin_amdgcn_readlane(m_rc[r], k);
+        P.total += (int)((r & 1) ? rcp >> 16 : rcp & 0xffff);
     }
     const int eb = __builtin_amdgcn_readlane(m_eb, k);
     P.vals = (const char *)a.values + (int64_t)eb * vbytes;
     P.keys = a.keys + eb;
-    P.dst0 = __builtin_amdgcn_readlane(m_dst0, k);
+    P.dst0b = __builtin_amdgcn_readlane(m_dst0, k) * (int)sizeof(unsigned long long);
     P.sa = ldexp((double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k)), shift);
 }
 
 // The row of entry e: a select chain over rows R, R + 1, ... (indices fixed at compile time, so
 // that the rows' values stay in registers rather than in an indexed private array).
 template <int L, int R>
-__device__ inline void row_select(const PairStep<L> &P, int e, int &o, int &drow)
+__device__ inline void row_select(const PairStep<L> &P, int e, int &o, int &drowb)
 {
     if constexpr (R < TileShape<L>::TB) {
         if (e >= P.ex[R]) {
             o = P.off[R];
-            drow = R * TileShape<L>::ROW;
+            drowb = R * TileShape<L>::ROW * (int)sizeof(unsigned long long);
         }
-        row_select<L, R + 1>(P, e, o, drow);
+        row_select<L, R + 1>(P, e, o, drowb);
     }
 }
 
-// Entry e of the pair (0 <= e < total): its stored value, and its LDS word.
+// Entry e of the pair (0 <= e < total): its stored value, and the byte address of its LDS word.
 template <int L, int VT>
-__device__ inline void pair_entry(const PairStep<L> &P, int e, float2 &v, int &word)
+__device__ inline void pair_entry(const PairStep<L> &P, int e, float2 &v, int &wbyte)
 {
     using S = TileShape<L>;
-    int o = P.off[0], drow = 0;
-    row_select<L, 1>(P, e, o, drow);
+    int o = P.off[0], drowb = 0;
+    row_select<L, 1>(P, e, o, drowb);
     const uint32_t rel = (uint32_t)(e + o);  // entry index within the plane's table
     if constexpr (VT == CGH_F32) {
         v = *reinterpret_cast<const float2 *>(P.vals + (rel << 3));
@@ -857,7 +860,14 @@ __device__ inline void pair_entry(const PairStep<L> &P, int e, float2 &v, int &w
             v = make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
         }
     }
-    word = P.dst0 + drow + *reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(P.keys) + (rel << 1));
+    wbyte = P.dst0b + drowb +
+            (int)*reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(P.keys) + (rel << 1)) *
+                (int)sizeof(unsigned long long);
+}
+
+__device__ inline void lds_add(unsigned long long *acc, int wbyte, unsigned long long v)
+{
+    atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(acc) + wbyte), v);
 }
 
 template <int L, int VT>
@@ -881,6 +891,10 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
         m_rc[r] = r < m_nrows ? m_rc[r] - m_rs[r] : 0;
         m_tot += m_rc[r];
     }
+    // row counts two to a register (a row of a pair holds at most 64 2^L <= 4096 entries)
+    int m_rcp[(S::TB + 1) / 2];
+#pragma unroll
+    for (int r = 0; r < S::TB; r += 2) m_rcp[r / 2] = m_rc[r] | (r + 1 < S::TB ? m_rc[r + 1] << 16 : 0);
     // the pairs with at least one entry, in order
     auto next_pair = [&](int k) {
         while (k < cnt && __builtin_amdgcn_readlane(m_tot, k) == 0) ++k;
@@ -888,7 +902,7 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
     };
     for (int k = next_pair(0); k < cnt; k = next_pair(k + 1)) {
         PairStep<L> P;
-        pair_setup<L, VT>(P, k, m_rs, m_rc, m_eb, m_dst0, m_amp, shift, a);
+        pair_setup<L, VT>(P, k, m_rs, m_rcp, m_eb, m_dst0, m_amp, shift, a);
         int c = 0;
         for (; P.total - c > 64; c += 128) {
             const int e0 = c + lane, e1 = e0 + 64;  // e0 < total
@@ -896,14 +910,14 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
             int w0, w1;
             pair_entry<L, VT>(P, e0, v0, w0);
             if (e1 < P.total) pair_entry<L, VT>(P, e1, v1, w1);
-            atomicAdd(&acc[w0], packed_fixed(v0, P.sa));
-            if (e1 < P.total) atomicAdd(&acc[w1], packed_fixed(v1, P.sa));
+            lds_add(acc, w0, packed_fixed(v0, P.sa));
+            if (e1 < P.total) lds_add(acc, w1, packed_fixed(v1, P.sa));
         }
         if (c + lane < P.total) {
             float2 v0;
             int w0;
             pair_entry<L, VT>(P, c + lane, v0, w0);
-            atomicAdd(&acc[w0], packed_fixed(v0, P.sa));
+            lds_add(acc, w0, packed_fixed(v0, P.sa));
         }
     }
 }
