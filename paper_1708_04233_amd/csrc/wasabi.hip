@@ -701,9 +701,9 @@ __device__ inline void unpack_fixed(unsigned long long w, int &re, int &im)
     re = (int)((long long)(w - (unsigned long long)(long long)im) >> 32);
 }
 
-// Adds the kept coefficients of one (tile, point) pair into the tile's LDS accumulators.  Called by
-// a whole wave with uniform arguments: the pair's table blocks inside the tile are `nrows` block
-// rows; row r's entries are the contiguous LUT range [rstart_r, rstart_r + rcount_r) (held by lane
+// Adds the kept coefficients of one (tile, point) pair into the tile's LDS accumulators, for L <= 2
+// (more than 8 block rows per pair; walk_pairs takes L >= 3).  Called by a whole wave with uniform
+// arguments: the pair's table blocks inside the tile are `nrows` block rows; row r's entries are the contiguous LUT range [rstart_r, rstart_r + rcount_r) (held by lane
 // r) and land at LDS element dst0 + r * ROW + key.  Each row is walked U x 64 entries at a time
 // with all loads issued before the LDS adds.
 template <int L, int VT>
@@ -713,47 +713,6 @@ __device__ inline void add_pair(unsigned long long *acc, const void *values, con
 {
     using S = TileShape<L>;
     const int lane = threadIdx.x & 63;
-    if constexpr (S::TB <= 8) {
-        // The rows' entry ranges are walked as one flat range of `total` entries (row r owns
-        // [ex_r, ex_r + count_r)), 64 lanes x 2 entries per step, all loads of a step issued
-        // before its adds; lanes past the end re-read the last entry and add 0 to their own word.
-        int ex[S::TB], off[S::TB];
-        int total = 0;
-#pragma unroll
-        for (int r = 0; r < S::TB; ++r) {
-            ex[r] = total;
-            off[r] = __builtin_amdgcn_readlane(rstart, r) - total;
-            total += __builtin_amdgcn_readlane(rcount, r);  // 0 for lanes >= nrows
-        }
-        for (int c = 0; c < total; c += 128) {
-            float2 v[2];
-            int key[2], drow[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = min(c + 64 * u + lane, total - 1);
-                int o = off[0];
-                drow[u] = 0;
-#pragma unroll
-                for (int r = 1; r < S::TB; ++r)
-                    if (e >= ex[r]) {
-                        o = off[r];
-                        drow[u] = r * S::ROW;
-                    }
-                const int64_t idx = (int64_t)eb + e + o;
-                v[u] = load_value<VT>(values, idx);
-                key[u] = keys[idx];
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const bool on = c + 64 * u + lane < total;
-                const double sa = on ? scaled_amp : 0.0;
-                const int at = on ? dst0 + drow[u] + key[u] : lane;
-                atomicAdd(&acc[at], packed_fixed(v[u], sa));
-            }
-        }
-        (void)nrows;
-        return;
-    }
     constexpr int U = 4;
     for (int r = 0; r < nrows; ++r) {
         const int rs = __builtin_amdgcn_readlane(rstart, r);
@@ -1052,8 +1011,13 @@ __device__ inline void fixed_mallat_store(const unsigned long long *acc, int e2,
     }
 }
 
+// At L <= 3 the pair walk holds more row values in scalar registers than 8 waves per SIMD leave
+// (about 100 SGPRs: 7 waves, i.e. 3 tiles of 8 waves per CU instead of 4); the occupancy hint
+// makes the compiler fit them (a few spills to VGPR lanes): 16384^2 FP16 5.53 -> 5.11 ms.  At
+// L >= 4 the kernel fits without it.
 template <int L, int VT, int MODE>
-__global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a)
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(L <= 3 ? 8 : 1, 8)))
+void tile_kernel(TileArgs a)
 {
     using S = TileShape<L>;
     constexpr int NW = kTileThreads / 64;

@@ -74,6 +74,29 @@ def test_superpose_matches_oracle(orc, levels, gamma, dtype):
     assert _rel(psi, want) < TOL
 
 
+@pytest.mark.parametrize("levels,nx", [(3, 200), (4, 208), (3, 64)])
+def test_superpose_into_unaligned_field(orc, levels, nx):
+    """The Mallat field written 8 bytes past a 16-byte boundary (coefficients stored one at a time
+    instead of two per store): bitwise the same as into an aligned field (fixed-point sums), and
+    equal to the oracle.  nx = 208 at L = 4 gives an odd scaling-band width (13)."""
+    ref, gpu = _luts(orc, levels, 0.25)
+    B = 1 << levels
+    ny = 136 // B * B
+    X0, Y0 = -B * 3, B
+    pts = _points(40 + levels, 60, nx + 160, ny + 160, B, x0=X0 - 80, y0=Y0 - 80)
+    q = _q_gpu(gpu, pts)
+    aligned = cgh.wasabi_superpose(gpu, q, X0, Y0, nx, ny)
+    flat = torch.full((nx * ny + 1,), complex("nan"), dtype=torch.complex64, device="cuda")
+    view = flat[1:].view(ny, nx)
+    assert view.data_ptr() % 16 == 8
+    cgh.wasabi_superpose(gpu, q, X0, Y0, nx, ny, psi=view)
+    torch.cuda.synchronize()
+    assert torch.equal(aligned, view)
+    assert torch.isnan(flat[0])                    # nothing written before the field
+    want = orc.superpose(ref, orc.quantize(pts, ref.params), X0, Y0, nx, ny)
+    assert _rel(aligned.cpu().numpy(), want) < TOL
+
+
 @pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6])
 def test_idwt_matches_oracle(orc, levels):
     B = 1 << levels
