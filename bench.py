@@ -30,6 +30,10 @@ from workloads import (DIRECT_512, WASABI_2048, WASABI_16384, WASABI_65536, grid
 
 METRIC = "hologram Mpixel·points/s WASABI vs direct @PSNR≥40dB; p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
+# VALU issue: each of the 256 CUs issues one wave64 VALU instruction per cycle (four SIMDs, each
+# spending four cycles of its 16 lanes on a wave64 instruction) at 2.4 GHz.  Times 64 lanes x 2
+# (FMA) x 2 (packed FP32) this is the FP32 vector peak of 157.3 TFLOP/s.
+VALU_PEAK_PER_S = 256 * 2.4e9
 GAMMA40_FILE = os.path.join(ROOT, "tests", "golden", "gamma40_2048.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
@@ -104,10 +108,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload, kernel, launches=1):
-    """HBM bytes per launch (times `launches`) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    passes (scaled by the copy calibration), or None when none were taken for this kernel source
-    and workload."""
+def counter_entry(workload, kernel):
+    """The committed rocprofv3 counter figures for this kernel and workload, or None when none were
+    taken for the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             table = json.load(f)
@@ -116,7 +119,27 @@ def counter_traffic(workload, kernel, launches=1):
     e = table.get(workload + "|" + kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
-    return e["traffic_bytes_per_launch"] * launches
+    return e
+
+
+def counter_traffic(workload, kernel, launches=1):
+    """HBM bytes per launch (times `launches`) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (scaled by the copy calibration), or None when none were taken for this kernel source
+    and workload."""
+    e = counter_entry(workload, kernel)
+    return None if e is None else e["traffic_bytes_per_launch"] * launches
+
+
+def valu_issue(workload, kernel, seconds_per_launch):
+    """VALU instructions per launch (committed SQ_INSTS_VALU pass) over the launch time measured
+    here, against the chip's issue peak; None when no pass was taken for this kernel source."""
+    e = counter_entry(workload, kernel)
+    if e is None or "valu_insts_per_launch" not in e:
+        return None
+    achieved = e["valu_insts_per_launch"] / seconds_per_launch
+    return {"bound": "alu", "insts_per_launch": e["valu_insts_per_launch"], "achieved": round(achieved, 1),
+            "peak": VALU_PEAK_PER_S, "unit": "wave64 VALU instructions/s",
+            "frac": round(achieved / VALU_PEAK_PER_S, 4)}
 
 
 def image_psnr(torch, cgh, u, ref, depths):
@@ -336,7 +359,8 @@ def main():
                 "traffic": traffic, "algorithmic_bytes": algo_bytes,
                 "scatter_adds": scatter, "scatter_adds_per_s": round(scatter / t_tile, 1),
                 "lut_stream_GBps": round(scatter * (10 if args.lut == "f32" else 6) / t_tile / 1e9, 1),
-                "ms_per_launch": round(kernels["tile_fused"], 4), "copy_GBps": copy_bandwidth(torch)}
+                "ms_per_launch": round(kernels["tile_fused"], 4), "copy_GBps": copy_bandwidth(torch),
+                "valu_issue": valu_issue("%s@%.2f" % (w["name"], g40), symbol, t_tile)}
 
     # ---- CPU baseline: the oracle on the same hologram ---------------------------------------
     cpu = None
@@ -477,7 +501,8 @@ def run_large(args, torch, cgh):
                            "achieved": round(algo / t_tile / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(algo / t_tile / 1e9 / HBM_PEAK_GBS, 4),
                            "traffic": counter_traffic("%s@%.2f" % (w["name"], g), symbol),
-                           "algorithmic_bytes": algo}
+                           "algorithmic_bytes": algo,
+                           "valu_issue": valu_issue("%s@%.2f" % (w["name"], g), symbol, t_tile)}
         if g == w["gamma"] and not tag:
             # the paper's procedure: sub-holograms (8192^2 for the 65536^2 case) superposed into a
             # wavelet field and inverted into their part of the hologram
@@ -517,7 +542,11 @@ def run_large(args, torch, cgh):
                                            "%s@%.2f-sub%d" % (w["name"], g, sub),
                                            "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt_run),
                                            sk["tile_superpose"][1]),
-                                       "algorithmic_bytes": algo}}
+                                       "algorithmic_bytes": algo,
+                                       "valu_issue": valu_issue(
+                                           "%s@%.2f-sub%d" % (w["name"], g, sub),
+                                           "%s<%d, %d, 0>" % ("dense_tile_kernel" if g >= 0.35 else "tile_kernel", L, vt_run),
+                                           sup_ms * 1e-3 / max(sk["tile_superpose"][1], 1))}}
         if tag:
             res["lut_values"] = "f16"
         results["gamma_%.2f%s" % (g, tag)] = res
