@@ -125,6 +125,22 @@ __device__ inline int sort_key(const wasabi_point &p, const SortKey &k)
     return p.depth * k.nyb + (int)b;
 }
 
+// Zeroes n 32-bit words.  The counters of the binning and of plane pacing are cleared with this
+// kernel rather than a memset, so that the path can be captured into a HIP graph and replayed.
+__global__ __launch_bounds__(256) void zero_words_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
+int zero_words(void *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return CGH_OK;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid), dim3(256), 0, s, (uint32_t *)p, n);
+    CGH_CHECK_LAUNCH("zero_words_kernel");
+    return CGH_OK;
+}
+
 template <bool LDS>
 __global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *pts, int64_t n,
                                                            SortKey key, int64_t chunk, int32_t *counts)
@@ -1472,7 +1488,7 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     if ((rc = sc.alloc((void **)&sorted, sizeof(wasabi_point) * std::max<int64_t>(n, 1)))) return rc;
     ProfScope prof("bin", s);
     // plane sort
-    CGH_TRY_HIP(hipMemsetAsync(dcounts, 0, sizeof(int32_t) * nbins, s));
+    if ((rc = zero_words(dcounts, nbins, s))) return rc;
     const bool lds_depth = nbins <= 4096;
     const int64_t dchunk = depth_chunk(n);
     const unsigned dgrid = (unsigned)std::max<int64_t>((n + dchunk - 1) / dchunk, 1);
@@ -1514,7 +1530,7 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
         hipLaunchKernelGGL(bin_fill_matrix_kernel, dim3((unsigned)nwg), dim3(kChunk), 0, s, sorted, n, lut->desc, nd, L, g, (int)nwg, chunk_pts(n), moff, list);
         CGH_CHECK_LAUNCH("bin_fill_matrix_kernel");
     } else {
-        CGH_TRY_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * ntiles, s));
+        if ((rc = zero_words(counts, ntiles, s))) return rc;
         const bool lds_tiles = ntiles <= kMaxLdsTiles;
         if (n > 0) {
             if (lds_tiles)
@@ -1697,7 +1713,7 @@ int launch_window(const wasabi_lut *lut, const Binned &b, int64_t ox, int64_t oy
         int *done;
         const size_t bytes = sizeof(int) * (size_t)lut->n_tables * kPaceCounters;
         if ((rc = sc.alloc((void **)&done, bytes))) return rc;
-        CGH_TRY_HIP(hipMemsetAsync(done, 0, bytes, s));
+        if ((rc = zero_words(done, (int64_t)lut->n_tables * kPaceCounters, s))) return rc;
         a.plane_done = done;
         a.pace_slack = std::max(1, slack_env);
     }
