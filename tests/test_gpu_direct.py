@@ -88,3 +88,18 @@ def test_2048_circ_sampled_pixels(orc):
         y0, x0 = (int(v) for v in rng.integers(0, w["nx"] - 16, 2))
         ref = orc.direct(pts, 16, 16, x0, y0, window=orc.CIRC)
         assert _rel(u[y0:y0 + 16, x0:x0 + 16].astype(np.complex128), ref) < 1e-5
+
+
+@pytest.mark.parametrize("window", ["full", "circ"])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_both_tile_shapes(orc, window, dtype):
+    """circ() windows of fewer than 2048 tiles of 64 x 16 pixels are summed with one row per thread
+    (64 x 4 tiles), larger ones and the full window with four: each against the oracle, with a
+    ragged last row of tiles."""
+    win = {"full": (cgh.FULL, orc.FULL), "circ": (cgh.CIRC, orc.CIRC)}[window]
+    tol = 1e-10 if dtype == torch.complex128 else 1e-5
+    for nx, ny in ((2048, 1036), (200, 70)):          # 32 x 65 tiles of 64 x 16; 4 x 5
+        pts = uniform_points(5, 12, nx, ny, 20e-6, 90e-6)
+        u = cgh.cgh_direct(torch.from_numpy(pts).cuda(), nx, ny, window=win[0], out_dtype=dtype)
+        ref = orc.direct(pts, nx, ny, window=win[1])
+        assert _rel(u.cpu().numpy().astype(np.complex128), ref) < tol, (nx, ny)
