@@ -16,7 +16,6 @@ namespace cgh {
 // Error reporting: every public entry point returns a cgh_status and leaves a thread-local text.
 // ---------------------------------------------------------------------------------------------
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-void clear_error();
 
 #define CGH_TRY_HIP(call)                                                                      \
     do {                                                                                       \

@@ -20,8 +20,6 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-void clear_error() { g_msg[0] = '\0'; }
-
 Scratch::~Scratch()
 {
     for (void *p : ptrs_) (void)hipFreeAsync(p, stream_);

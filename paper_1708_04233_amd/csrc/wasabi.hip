@@ -508,13 +508,6 @@ __device__ inline void load_wide(const void *values, int64_t i, float2 *out)
     }
 }
 
-// Address of element i of a value array (FP32: float2 elements; FP16/BF16: packed 32-bit pairs).
-template <int VT>
-__device__ inline const void *value_at(const void *values, int64_t i)
-{
-    return (const char *)values + i * (VT == CGH_F32 ? 8 : 4);
-}
-
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 
@@ -711,17 +704,12 @@ __device__ inline unsigned long long packed_fixed(float2 v, double scaled_amp)
     return ((unsigned long long)hi << 32) | (unsigned)im;
 }
 
-__device__ inline void unpack_fixed(unsigned long long w, int &re, int &im)
-{
-    im = (int)(unsigned)(w & 0xffffffffull);
-    re = (int)((long long)(w - (unsigned long long)(long long)im) >> 32);
-}
-
 // Adds the kept coefficients of one (tile, point) pair into the tile's LDS accumulators, for L <= 2
 // (more than 8 block rows per pair; walk_pairs takes L >= 3).  Called by a whole wave with uniform
-// arguments: the pair's table blocks inside the tile are `nrows` block rows; row r's entries are the contiguous LUT range [rstart_r, rstart_r + rcount_r) (held by lane
-// r) and land at LDS element dst0 + r * ROW + key.  Each row is walked U x 64 entries at a time
-// with all loads issued before the LDS adds.
+// arguments: the pair's table blocks inside the tile are `nrows` block rows; row r's entries are
+// the contiguous LUT range [rstart_r, rstart_r + rcount_r) (held by lane r) and land at LDS
+// element dst0 + r * ROW + key.  Each row is walked U x 64 entries at a time with all loads issued
+// before the LDS adds; lanes past the end of a row are masked off.
 template <int L, int VT>
 __device__ inline void add_pair(unsigned long long *acc, const void *values, const uint16_t *keys,
                                 int eb, int dst0, int nrows, double scaled_amp, int rstart,
@@ -903,7 +891,7 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
 __device__ inline float2 fixed_value(unsigned long long w, int e2)
 {
     const unsigned lo = (unsigned)w, hi = (unsigned)(w >> 32);
-    const int im = (int)lo, re = (int)(hi - (unsigned)(im >> 31));  // see unpack_fixed
+    const int im = (int)lo, re = (int)(hi - (unsigned)(im >> 31));  // undoes packed_fixed
     return make_float2(ldexpf((float)re, e2), ldexpf((float)im, e2));
 }
 
@@ -1037,8 +1025,7 @@ void tile_kernel(TileArgs a)
 {
     using S = TileShape<L>;
     constexpr int NW = kTileThreads / 64;
-    // packed fixed-point (re, im) words; lanes past the end of a range add zero to word `lane`,
-    // one word per lane so that they do not collide
+    // packed fixed-point (re, im) words
     __shared__ unsigned long long acc[S::N];
     const int tile = blockIdx.x;
     int ty, tx;
