@@ -32,6 +32,8 @@ struct DirectArgs {
     double pitch, inv_lambda, tan2;  // tan2 = tan(theta)^2
     void *out;
     int64_t ld;
+    int64_t chunk;        // points per blockIdx.z slice (n when the points are not split)
+    int64_t part_stride;  // split: slice z writes its partial field at out + z * part_stride (ld = nx)
 };
 
 // A workgroup sums a 64 x 4 ROWS pixel tile: wave w owns rows w, w + 4, ... of it, lane l column l.
@@ -68,12 +70,14 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a)
         accf_re[k] = accf_im[k] = 0.0f;
     }
 
-    for (int64_t base = 0; base < a.n; base += kThreads) {
+    // this workgroup's slice of the points (all of them unless the sum is split over blockIdx.z)
+    const int64_t j0 = (int64_t)blockIdx.z * a.chunk, j1 = min(a.n, j0 + a.chunk);
+    for (int64_t base = j0; base < j1; base += kThreads) {
         const int64_t j = base + tid;
         bool keep = false;
         double4 p = make_double4(0, 0, 0, 0);
         double r2 = 0.0;
-        if (j < a.n) {
+        if (j < j1) {
             p = a.pts[j];
             r2 = p.z * p.z * a.tan2;
             keep = true;
@@ -145,15 +149,31 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a)
         for (int rr = 0; rr < ROWS; rr++) {
             const int row = row0 + 4 * rr;
             if (row >= a.ny) continue;
+            const int64_t at = (int64_t)blockIdx.z * a.part_stride + (int64_t)row * a.ld + col;
             if (F64) {
-                double2 *o = (double2 *)a.out;
-                o[(int64_t)row * a.ld + col] = make_double2(accd_re[rr], accd_im[rr]);
+                ((double2 *)a.out)[at] = make_double2(accd_re[rr], accd_im[rr]);
             } else {
-                float2 *o = (float2 *)a.out;
-                o[(int64_t)row * a.ld + col] = make_float2(accf_re[rr], accf_im[rr]);
+                ((float2 *)a.out)[at] = make_float2(accf_re[rr], accf_im[rr]);
             }
         }
     }
+}
+
+// Sums the nsplit partial fields (nx x ny each, contiguous) in slice order into the output.
+template <typename T>
+__global__ __launch_bounds__(256) void sum_parts_kernel(const T *part, int nsplit, int32_t nx, int32_t ny,
+                                                        T *out, int64_t ld)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)nx * ny) return;
+    const int64_t plane = (int64_t)nx * ny;
+    T acc = part[i];
+    for (int z = 1; z < nsplit; ++z) {
+        const T v = part[z * plane + i];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    out[(i / nx) * ld + i % nx] = acc;
 }
 
 // ---- circ() window at scale: points binned by 64 x 16 tile (tiles their disk reaches), then each
@@ -374,6 +394,8 @@ extern "C" int cgh_direct(const double *pts, int64_t n, int32_t nx, int32_t ny, 
     a.tan2 = sin_t * sin_t / (1.0 - sin_t * sin_t);
     a.out = out;
     a.ld = ld_out;
+    a.chunk = std::max<int64_t>(n, 1);
+    a.part_stride = 0;
     const bool f64 = out_dtype == CGH_C128, circ = window == CGH_CIRC;
     dim3 grid((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY);
     // circ() with fewer than 8 workgroups per CU of 64 x 16 pixels: tiles of 64 x 4 instead, which
@@ -387,7 +409,39 @@ extern "C" int cgh_direct(const double *pts, int64_t n, int32_t nx, int32_t ny, 
     const bool bin = force ? atoi(force) != 0 : (double)n * grid.x * grid.y > 2e9;
     if (circ && bin) return direct_binned(a, sin_t / std::sqrt(1.0 - sin_t * sin_t), f64, s);
     if (grid.y > 65535) return fail(CGH_EINVAL, "ny too large");
+    // The full window on fewer than 4 workgroups per CU: the points are split over up to 4 slices
+    // (blockIdx.z), each summing into a partial field, and the partial fields are added in slice
+    // order afterwards (512^2, N = 10^3: one wave per SIMD otherwise).
+    int nsplit = 1;
+    const int64_t wgs = (int64_t)grid.x * grid.y;
+    if (!circ && wgs < 1024) nsplit = (int)std::min<int64_t>(std::min<int64_t>(4, (1024 + wgs - 1) / wgs), (n + 255) / 256);
+    nsplit = std::max(nsplit, 1);
     ProfScope prof("direct", s);
+    if (nsplit > 1) {
+        int rc = prepare_pool();
+        if (rc) return rc;
+        Scratch sc(s);
+        const size_t elem = f64 ? sizeof(double2) : sizeof(float2);
+        void *part;
+        if ((rc = sc.alloc(&part, elem * (size_t)nsplit * nx * ny))) return rc;
+        a.out = part;
+        a.ld = nx;
+        a.part_stride = (int64_t)nx * ny;
+        a.chunk = (n + nsplit - 1) / nsplit;
+        const dim3 gz(grid.x, grid.y, (unsigned)nsplit);
+        if (f64) hipLaunchKernelGGL((direct_kernel<false, true, kRows>), gz, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((direct_kernel<false, false, kRows>), gz, dim3(kThreads), 0, s, a);
+        CGH_CHECK_LAUNCH("direct_kernel");
+        const unsigned rb = (unsigned)(((int64_t)nx * ny + 255) / 256);
+        if (f64)
+            hipLaunchKernelGGL(sum_parts_kernel<double2>, dim3(rb), dim3(256), 0, s, (const double2 *)part, nsplit, nx, ny,
+                               (double2 *)out, ld_out);
+        else
+            hipLaunchKernelGGL(sum_parts_kernel<float2>, dim3(rb), dim3(256), 0, s, (const float2 *)part, nsplit, nx, ny,
+                               (float2 *)out, ld_out);
+        CGH_CHECK_LAUNCH("sum_parts_kernel");
+        return CGH_OK;
+    }
     if (one_row && f64) {
         hipLaunchKernelGGL((direct_kernel<true, true, 1>), grid1, dim3(kThreads), 0, s, a);
     } else if (one_row) {

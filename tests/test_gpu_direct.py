@@ -103,3 +103,15 @@ def test_both_tile_shapes(orc, window, dtype):
         u = cgh.cgh_direct(torch.from_numpy(pts).cuda(), nx, ny, window=win[0], out_dtype=dtype)
         ref = orc.direct(pts, nx, ny, window=win[1])
         assert _rel(u.cpu().numpy().astype(np.complex128), ref) < tol, (nx, ny)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_full_window_split_over_points(orc, dtype):
+    """A small full window is summed in up to four slices of the points whose partial fields are
+    added afterwards: 3000 points over a 200 x 70 window (slices of 750, not a multiple of the
+    256-point batches) against the oracle."""
+    nx, ny = 200, 70
+    pts = uniform_points(8, 3000, nx, ny, 20e-6, 90e-6)
+    u = cgh.cgh_direct(torch.from_numpy(pts).cuda(), nx, ny, window=cgh.FULL, out_dtype=dtype)
+    ref = orc.direct(pts, nx, ny, window=orc.FULL)
+    assert _rel(u.cpu().numpy().astype(np.complex128), ref) < (1e-10 if dtype == torch.complex128 else 1e-5)
