@@ -32,6 +32,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# The test of the pins themselves (tests/test_oracle_mutations.py) runs the pin suite against
+# copies of oracle.c compiled with one planted mistake each, named by this variable.
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIB_OVERRIDE")
 _lib = None
 
 F32, F16, BF16, F64 = 0, 1, 2, 3
@@ -53,9 +56,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build(force=False)
-    lib = ctypes.CDLL(_LIB_PATH)
+    if _LIB_OVERRIDE:
+        lib = ctypes.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.oracle_direct.argtypes = [P, I64, I32, I32, I64, I64, D, D, I32, P]
     lib.oracle_direct.restype = None
@@ -306,11 +312,14 @@ def wasabi(lut: Lut, q: Quantized, X0: int, Y0: int, nx: int, ny: int) -> np.nda
 # Quality measures (definitions of the design notes; the paper prints none)
 # ----------------------------------------------------------------------------------------------
 def rel_l2(u: np.ndarray, ref: np.ndarray) -> float:
+    """||u - ref||_2 / ||ref||_2 over all elements (the reference in the denominator)."""
     return float(np.linalg.norm((u - ref).ravel()) / np.linalg.norm(ref.ravel()))
 
 
 def psnr(u: np.ndarray, ref: np.ndarray) -> float:
-    """10 log10(max|ref|^2 / mean|u - ref|^2) on the complex field."""
+    """10 log10(max|ref|^2 / mean|u - ref|^2) on the complex field: the peak power of the
+    reference over the mean power of the error (the paper prints no quality figure; this is the
+    reading the tests and the selectivity sweep use)."""
     mse = float(np.mean(np.abs(u - ref) ** 2))
     peak = float(np.max(np.abs(ref)) ** 2)
     return float("inf") if mse == 0 else 10.0 * np.log10(peak / mse)

@@ -45,6 +45,29 @@ def test_circ_support_is_gauss_lattice_count(orc):
     np.testing.assert_array_equal(u[mask], full[mask])
 
 
+def test_circ_boundary_is_strict(orc):
+    """circ(c) = 1 only for c < 1 (Sec. 2, step 1): a pixel exactly on the PSF's rim is outside.
+    With pitch 1 and lambda 1.2 (any unit), tan(theta) = 0.75 and z = 5 / tan(theta) make
+    R^2 = 25 exactly in FP64, so the 12 pixels at squared distance 25 (offsets (+-3, +-4),
+    (+-4, +-3), (+-5, 0), (0, +-5)) lie on the rim: the disk holds sum_{n<25} r2(n) = 69 pixels."""
+    p, lam = 1.0, 1.2
+    s = lam / (2.0 * p)
+    tan_t = s / np.sqrt(1.0 - s * s)
+    z = 5.0 / tan_t
+    assert (z * tan_t) * (z * tan_t) == 25.0          # the rim is hit exactly in FP64
+    pts = np.array([[8.0, 8.0, z, 1.0]])
+    u = orc.direct(pts, nx=17, ny=17, pitch=p, wavelength=lam, window=orc.CIRC)
+    inside = sum(_jacobi_r2(n) for n in range(25))
+    assert inside == 69 and _jacobi_r2(25) == 12
+    assert int(np.count_nonzero(u)) == inside
+    for dx, dy in ((3, 4), (4, -3), (-5, 0), (0, 5)):
+        assert u[8 + dy, 8 + dx] == 0
+    assert abs(u[8 + 4, 8 + 2]) > 0.5                  # squared distance 20, inside
+    # the pre-computed PSF table draws the same rim: R = 5 exactly, the same 69 pixels
+    T = orc.psf_table(z, 5.0, 16, pitch=p, wavelength=lam)
+    assert int(np.count_nonzero(T)) == inside
+
+
 def test_linearity_in_amplitude(orc):
     rng = np.random.default_rng(1)
     pts = np.stack([rng.uniform(0, 24e-6, 5), rng.uniform(0, 24e-6, 5),
