@@ -81,9 +81,12 @@ int cgh_direct(const double *pts_dev, int64_t n, int32_t nx, int32_t ny, int64_t
  * sampled on a W_d x W_d table centred on pixel W_d / 2, W_d = the smallest multiple of 2^(L+1)
  * with W_d >= 2 floor(R_d) + 2.  The table gets an L-level orthonormal Haar transform, and the
  * N_r(d) = ceil(gamma pi R_d^2) coefficients of largest magnitude (clamped to [1, W_d^2]; all
- * W_d^2 when gamma >= 1) are kept, values rounded to `value_dtype`.  Magnitude ties are broken
- * by the library's internal coefficient order, so two correct LUTs may differ at the threshold.
- * The PSF phase, transform and selection are computed in FP64.
+ * W_d^2 when gamma >= 1) are kept, values rounded to `value_dtype`.  The PSF phase and the
+ * transform are computed in FP64; the ranking key is the strength |c|^2, computed in FP64 and
+ * rounded to FP32, and equal keys go to the lower flat table index (row * W_d + col), so the kept
+ * set is unique: any implementation of this rule keeps the same coefficients.  The LUT needs fewer
+ * than 2^31 kept coefficients and fewer than 2^31 Haar blocks over all tables (else CGH_EINVAL,
+ * returned before anything is allocated).
  * Phase tables (phases = 1): Eq.(2) moves a table by whole 2^L blocks, so a plane's single table
  * places only points on the 2^L grid.  With phase tables every plane gets 4^L tables, one per
  * position (sx, sy) of a point inside its 2^L x 2^L block (0 <= sx, sy < 2^L): table
@@ -175,17 +178,25 @@ int wasabi_quantize(const wasabi_lut *lut, const double *pts_dev, int64_t n,
  * x'_j = x_j - ox, y'_j = y_j - oy.  Every kept coefficient of every valid point is added at its
  * level-scaled position; coefficients that land outside the window are dropped (exact for
  * Haar: the result equals the same window of a larger hologram).
- *   psi_dev : device, ny x nx complex64 in Mallat layout (level-l bands of (ny>>l) x (nx>>l):
- *             H at (0, nx>>l), V at (ny>>l, 0), D at (ny>>l, nx>>l), scaling band at (0, 0)),
- *             overwritten.  FP32 accumulation.
+ *   psi_dev    : device, ny x nx complex64 in Mallat layout (level-l bands of (ny>>l) x (nx>>l):
+ *                H at (0, nx>>l), V at (ny>>l, 0), D at (ny>>l, nx>>l), scaling band at (0, 0)).
+ *                FP32 accumulation.
+ *   accumulate : 0 -- psi is overwritten with this call's field;
+ *                1 -- this call's field is added to the values psi holds (one FP32 addition per
+ *                coefficient), so a field can be built from several point sets in turn.
  * Requires ox, oy, nx, ny multiples of 2^L, nx, ny >= 2^L.
- * Errors: CGH_EINVAL, CGH_ENOMEM, CGH_EHIP. */
+ * Errors: CGH_EINVAL (also accumulate not 0 or 1), CGH_ENOMEM, CGH_EHIP. */
 int wasabi_superpose(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t n, int64_t ox,
-                     int64_t oy, int32_t nx, int32_t ny, void *psi_dev, void *stream);
+                     int64_t oy, int32_t nx, int32_t ny, void *psi_dev, int32_t accumulate,
+                     void *stream);
 
 /* Inverse L-level orthonormal Haar transform (Sec. 2, step 3): psi (ny x nx complex64, Mallat
- * layout, contiguous) -> u (ny rows of nx complex64, row stride ld_u elements).  u must not
- * overlap psi.  Requires nx, ny multiples of 2^L.  Errors: CGH_EINVAL, CGH_EHIP. */
+ * layout, contiguous) -> u (ny rows of nx complex64, row stride ld_u elements).
+ * In place: u_dev == psi_dev with ld_u == nx overwrites the field with the hologram.  The inverse
+ * moves every coefficient to pixels of another part of the field, so the in-place call first
+ * copies psi to 8 nx ny bytes of scratch from the stream-ordered pool (twice the device-memory
+ * traffic of the out-of-place call).  Any other overlap of u and psi is CGH_EINVAL.
+ * Requires nx, ny multiples of 2^L.  Errors: CGH_EINVAL, CGH_ENOMEM (in place), CGH_EHIP. */
 int wasabi_idwt(const void *psi_dev, int32_t nx, int32_t ny, int32_t levels, void *u_dev,
                 int64_t ld_u, void *stream);
 
@@ -317,9 +328,11 @@ int cgh_server_wait(cgh_server *srv, uint64_t ticket, int32_t timeout_ms, cgh_re
  * memory.  Errors: CGH_ENOTFOUND, CGH_EINVAL (the job has already ended: release it instead). */
 int cgh_server_cancel(cgh_server *srv, uint64_t ticket);
 
-/* Forget an ended job and give its result memory back to the budget.  The caller must have
- * finished (synchronised) any device work that reads the result.  Errors: CGH_ENOTFOUND,
- * CGH_EAGAIN (the job has not ended yet). */
+/* Forget an ended job and give its result memory back to the budget.  The result buffer is freed
+ * in the order of the job's own stream only, and the server may hand the memory to its next job
+ * at once: the caller must therefore have finished (synchronised) every stream whose device work
+ * reads the result before calling this.  Errors: CGH_ENOTFOUND, CGH_EAGAIN (the job has not ended
+ * yet). */
 int cgh_server_release(cgh_server *srv, uint64_t ticket);
 
 /* Current counters.  Errors: CGH_EINVAL. */

@@ -99,7 +99,7 @@ def load() -> ctypes.CDLL:
         "wasabi_lut_export": ([P, P, P, P], ctypes.c_int),
         "wasabi_lut_free": ([P], None),
         "wasabi_quantize": ([P, P, I64, P, P], ctypes.c_int),
-        "wasabi_superpose": ([P, P, I64, I64, I64, I32, I32, P, P], ctypes.c_int),
+        "wasabi_superpose": ([P, P, I64, I64, I64, I32, I32, P, I32, P], ctypes.c_int),
         "wasabi_idwt": ([P, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram": ([P, P, I64, I64, I64, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram_fused": ([P, P, I64, I64, I64, I32, I32, P, I64, P], ctypes.c_int),
@@ -286,16 +286,21 @@ def wasabi_quantize(lut: Lut, pts: torch.Tensor, out: torch.Tensor | None = None
 
 
 def wasabi_superpose(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, ny: int,
-                     psi: torch.Tensor | None = None) -> torch.Tensor:
+                     psi: torch.Tensor | None = None, accumulate: bool = False) -> torch.Tensor:
+    """Eq.(2) into psi (Mallat layout); accumulate=True adds to the values psi already holds."""
     n = q.shape[0]
     if psi is None:
+        if accumulate:
+            raise ValueError("accumulate needs psi")
         psi = torch.empty((ny, nx), dtype=torch.complex64, device=q.device)
     _check(load().wasabi_superpose(lut.handle, _dev(q, "points", torch.int32, (n, 4)), n, ox, oy,
-                                   nx, ny, _dev(psi, "psi", torch.complex64, (ny, nx)), _stream()))
+                                   nx, ny, _dev(psi, "psi", torch.complex64, (ny, nx)),
+                                   1 if accumulate else 0, _stream()))
     return psi
 
 
 def wasabi_idwt(psi: torch.Tensor, levels: int, u: torch.Tensor | None = None) -> torch.Tensor:
+    """Inverse Haar of the Mallat field psi into u; u may be psi itself (in place)."""
     ny, nx = psi.shape
     if u is None:
         u = torch.empty((ny, nx), dtype=torch.complex64, device=psi.device)
@@ -406,6 +411,11 @@ class Server:
         _check(load().cgh_server_cancel(self.handle, ticket))
 
     def release(self, ticket: int):
+        """Give the job's result back.  Work that torch queued on the current stream (a clone of the
+        result, say) may still read it, and the server may hand the memory to its next job at once,
+        so that stream is synchronised first (when torch has touched the GPU at all)."""
+        if torch.cuda.is_initialized():
+            torch.cuda.current_stream().synchronize()
         _check(load().cgh_server_release(self.handle, ticket))
 
     def stats(self) -> dict:

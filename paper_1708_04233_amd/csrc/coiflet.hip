@@ -78,7 +78,7 @@ int coiflet_hologram(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, 
         for (int64_t s0 = 0; s0 < nx; s0 += sub) {
             const int32_t wx = (int32_t)std::min<int64_t>(sub, nx - s0) + 2 * H;
             const int32_t wy = (int32_t)std::min<int64_t>(sub, ny - t0) + 2 * H;
-            if ((rc = wasabi_superpose(lut, pts, n, ox + s0 - H, oy + t0 - H, wx, wy, A, s))) return rc;
+            if ((rc = wasabi_superpose(lut, pts, n, ox + s0 - H, oy + t0 - H, wx, wy, A, 0, s))) return rc;
             {
                 ProfScope prof("coiflet_idwt", s);
                 for (int l = L - 1; l >= 0; --l) {

@@ -137,6 +137,9 @@ int lut_geometry(wasabi_lut *lut)
     lut->P = p.phases ? 1 << (2 * p.levels) : 1;
     lut->n_tables = n * lut->P;
     const int P = lut->P, nt = lut->n_tables;
+    // The superposition addresses entries and per-block offsets with 32-bit integers: both totals
+    // are bounded here, before anything is allocated.
+    int64_t blk_total = 0, entries = 0;
     lut->z.resize(nt);
     lut->R.resize(nt);
     lut->W.resize(nt);
@@ -167,6 +170,13 @@ int lut_geometry(wasabi_lut *lut)
             if (nr < 1) nr = 1;
             if (nr > all) nr = all;
         }
+        blk_total += (int64_t)P * ((W / B) * (W / B) + 1);
+        entries += (int64_t)P * nr;
+        if (blk_total >= INT32_MAX)
+            return fail(CGH_EINVAL, "LUT of more than 2^31 - 1 Haar blocks (%d tables of up to %lld^2 pixels)", nt,
+                        (long long)W);
+        if (entries >= INT32_MAX)
+            return fail(CGH_EINVAL, "LUT of more than 2^31 - 1 kept coefficients");
         for (int t = d * P; t < (d + 1) * P; ++t) {
             lut->z[t] = z;
             lut->R[t] = R;

@@ -446,6 +446,7 @@ struct TileArgs {
     int *plane_done;            // plane pacing: tiles that finished plane d (NULL = off)
     int pace_slack;             // a tile starts plane d once all tiles finished plane d - slack
     int stream_psi;             // MODE_PSI: the Mallat field is written past the caches
+    int accumulate;             // MODE_PSI: add to the field's values instead of overwriting them
 };
 
 template <int L>
@@ -511,9 +512,14 @@ __device__ inline void load_wide(const void *values, int64_t i, float2 *out)
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 
-// Stores one complex value of a Mallat field through the caches or (nt) past them.
-__device__ inline void put2(float2 *p, float2 v, bool nt)
+// Stores one complex value of a Mallat field through the caches or (nt) past them; with `acc` the
+// value is added to the one already there.
+__device__ inline void put2(float2 *p, float2 v, bool nt, bool acc)
 {
+    if (acc) {
+        const float2 o = *p;
+        v = make_float2(o.x + v.x, o.y + v.y);
+    }
     if (nt)
         __builtin_nontemporal_store((v2f){v.x, v.y}, reinterpret_cast<v2f *>(p));
     else
@@ -573,7 +579,7 @@ __device__ inline void tile_mallat_load(float *sre, float *sim, const float2 *fi
 // Moves the tile's coefficients between LDS and the window's Mallat layout (rows of nx).
 template <int L, bool TO_LDS, int NT>
 __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, const TileGeom &g,
-                                      int ty, int tx, int th, int tw)
+                                      int ty, int tx, int th, int tw, bool add = false)
 {
     using S = TileShape<L>;
     const int64_t nx = g.nx;
@@ -595,7 +601,7 @@ __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, con
                     sre[at] = v.x;
                     sim[at] = v.y;
                 } else {
-                    *f = make_float2(sre[at], sim[at]);
+                    put2(f, make_float2(sre[at], sim[at]), false, add);
                 }
             }
         }
@@ -613,7 +619,7 @@ __device__ inline void tile_mallat_io(float *sre, float *sim, float2 *field, con
                 sre[at] = v.x;
                 sim[at] = v.y;
             } else {
-                *f = make_float2(sre[at], sim[at]);
+                put2(f, make_float2(sre[at], sim[at]), false, add);
             }
         }
     }
@@ -985,7 +991,8 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, int e2, floa
 // The tile's coefficients from its fixed-point words straight into the window's Mallat layout.
 template <int L, int NT>
 __device__ inline void fixed_mallat_store(const unsigned long long *acc, int e2, float2 *field,
-                                          const TileGeom &g, int ty, int tx, int th, int tw, bool nt)
+                                          const TileGeom &g, int ty, int tx, int th, int tw, bool nt,
+                                          bool add)
 {
     using S = TileShape<L>;
     const int64_t nx = g.nx;
@@ -1001,7 +1008,7 @@ __device__ inline void fixed_mallat_store(const unsigned long long *acc, int e2,
                 if (m >= hb || n >= wb) continue;
                 const int code = (((band & 2) ? h : 0) + (m & (h - 1))) * S::B + ((band & 1) ? h : 0) + (n & (h - 1));
                 put2(field + (row0 + (int64_t)ty * wf + m) * nx + col0 + (int64_t)tx * wf + n,
-                     fixed_value(acc[(m / h) * S::ROW + (n / h) * S::BS + code], e2), nt);
+                     fixed_value(acc[(m / h) * S::ROW + (n / h) * S::BS + code], e2), nt, add);
             }
         }
     }
@@ -1011,7 +1018,7 @@ __device__ inline void fixed_mallat_store(const unsigned long long *acc, int e2,
         const int m = i / wf, n = i % wf;
         if (m >= hb || n >= wb) continue;
         put2(field + ((int64_t)ty * wf + m) * nx + (int64_t)tx * wf + n, fixed_value(acc[m * S::ROW + n * S::BS], e2),
-             nt);
+             nt, add);
     }
 }
 
@@ -1115,7 +1122,8 @@ void tile_kernel(TileArgs a)
 
     const int e2 = -shift;  // the words hold value * 2^shift
     if constexpr (MODE == MODE_PSI)
-        fixed_mallat_store<L, kTileThreads>(acc, e2, a.out, a.g, ty, tx, th, tw, a.stream_psi != 0);
+        fixed_mallat_store<L, kTileThreads>(acc, e2, a.out, a.g, ty, tx, th, tw, a.stream_psi != 0,
+                                            a.accumulate != 0);
     else
         fixed_inverse_store<L, kTileThreads>(acc, e2, a.out, a.ld, ty, tx, th, tw);
 }
@@ -1325,7 +1333,7 @@ void dense_tile_kernel(TileArgs a)
     }
     __syncthreads();
     if (MODE == MODE_PSI) {
-        tile_mallat_io<L, false, kDenseThreads>(sre, sim, a.out, a.g, ty, tx, th, tw);
+        tile_mallat_io<L, false, kDenseThreads>(sre, sim, a.out, a.g, ty, tx, th, tw, a.accumulate != 0);
     } else {
         tile_inverse_and_store<L, kDenseThreads>(sre, sim, a.out, a.ld, ty, tx, th, tw);
     }
@@ -1620,6 +1628,7 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.plane_done = nullptr;
     a.pace_slack = 5;
     a.stream_psi = 0;
+    a.accumulate = 0;
     return a;
 }
 
@@ -1678,7 +1687,8 @@ int bin_window(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_
 // Superposition of the window (ox, oy, nx, ny) from the lists of `b`, whose window holds this one
 // with this one's origin on its tile grid.
 int launch_window(const wasabi_lut *lut, const Binned &b, int64_t ox, int64_t oy, int32_t nx, int32_t ny,
-                  void *out, int64_t ld, int mode, hipStream_t s, bool allow_pace, Scratch &sc)
+                  void *out, int64_t ld, int mode, hipStream_t s, bool allow_pace, Scratch &sc,
+                  int accumulate = 0)
 {
     TileGeom g = make_geom(ox, oy, nx, ny);
     g.cell = b.g.cell;
@@ -1689,6 +1699,7 @@ int launch_window(const wasabi_lut *lut, const Binned &b, int64_t ox, int64_t oy
     TileArgs a = make_args(lut, b.sorted, b.tile_off, b.tile_pts, g, (float2 *)out, ld);
     a.cell_bound = b.cell_bound;
     a.stream_psi = mode == MODE_PSI && streams_past_cache(nx, ny);
+    a.accumulate = mode == MODE_PSI && accumulate;
     // Plane pacing (bounded waits; see the dense kernel) when the lists are in plane order and
     // every tile of the grid is resident at once.  CGH_PACE=0 switches it off, CGH_PACE_SLACK sets
     // how many planes a tile may run ahead of the slowest one.
@@ -1710,15 +1721,15 @@ int launch_window(const wasabi_lut *lut, const Binned &b, int64_t ox, int64_t oy
 
 int superpose_impl(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox,
                    int64_t oy, int32_t nx, int32_t ny, void *out, int64_t ld, int mode,
-                   hipStream_t s, bool allow_pace = true, Scratch *ext = nullptr)
+                   hipStream_t s, bool allow_pace = true, Scratch *ext = nullptr, int accumulate = 0)
 {
-    int rc = prepare_pool();
+    int rc = ext ? CGH_OK : prepare_pool();
     if (rc) return rc;
     Scratch local(s);
     Scratch &sc = ext ? *ext : local;
     Binned b;
     if ((rc = bin_window(lut, pts, n, ox, oy, nx, ny, sc, s, b))) return rc;
-    return launch_window(lut, b, ox, oy, nx, ny, out, ld, mode, s, allow_pace, sc);
+    return launch_window(lut, b, ox, oy, nx, ny, out, ld, mode, s, allow_pace, sc, accumulate);
 }
 
 int check_common(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox, int64_t oy,
@@ -1792,12 +1803,14 @@ int hologram_fused_shared(const wasabi_lut *lut, const wasabi_point *pts, int64_
 
 extern "C" int wasabi_superpose(const wasabi_lut *lut, const wasabi_point *pts, int64_t n,
                                 int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *psi,
-                                void *stream)
+                                int32_t accumulate, void *stream)
 {
     using namespace cgh;
     int rc = check_common(lut, pts, n, ox, oy, nx, ny, psi);
     if (rc) return rc;
-    return superpose_impl(lut, pts, n, ox, oy, nx, ny, psi, nx, MODE_PSI, (hipStream_t)stream);
+    if (accumulate != 0 && accumulate != 1) return fail(CGH_EINVAL, "accumulate must be 0 or 1");
+    return superpose_impl(lut, pts, n, ox, oy, nx, ny, psi, nx, MODE_PSI, (hipStream_t)stream, true,
+                          nullptr, accumulate);
 }
 
 extern "C" int wasabi_idwt(const void *psi, int32_t nx, int32_t ny, int32_t levels, void *u,
@@ -1809,8 +1822,24 @@ extern "C" int wasabi_idwt(const void *psi, int32_t nx, int32_t ny, int32_t leve
     int rc = check_window(levels, 0, 0, nx, ny);
     if (rc) return rc;
     if (ld_u < nx) return fail(CGH_EINVAL, "ld_u < nx");
-    if (psi == u) return fail(CGH_EINVAL, "u must not overlap psi");
-    return idwt_impl(psi, nx, ny, levels, u, ld_u, (hipStream_t)stream);
+    const uintptr_t pb = (uintptr_t)psi, ub = (uintptr_t)u;
+    const uintptr_t pe = pb + sizeof(float2) * (uintptr_t)nx * (uintptr_t)ny;
+    const uintptr_t ue = ub + sizeof(float2) * ((uintptr_t)(ny - 1) * (uintptr_t)ld_u + (uintptr_t)nx);
+    const bool in_place = psi == u && ld_u == nx;
+    if (pb < ue && ub < pe && !in_place)
+        return fail(CGH_EINVAL, "u overlaps psi without being the same contiguous array (in place needs u == psi, ld_u == nx)");
+    hipStream_t s = (hipStream_t)stream;
+    if (!in_place) return idwt_impl(psi, nx, ny, levels, u, ld_u, s);
+    // In place.  A tile's pixels land where the Mallat layout keeps coefficients of other tiles
+    // (the inverse is a global permutation of the field), so the field is first copied to scratch
+    // and the inverse reads the copy: 8 nx ny bytes of scratch and twice the traffic of the
+    // out-of-place call.
+    if ((rc = prepare_pool())) return rc;
+    Scratch sc(s);
+    void *copy;
+    if ((rc = sc.alloc(&copy, sizeof(float2) * (size_t)nx * ny))) return rc;
+    CGH_TRY_HIP(hipMemcpyAsync(copy, psi, sizeof(float2) * (size_t)nx * ny, hipMemcpyDeviceToDevice, s));
+    return idwt_impl(copy, nx, ny, levels, u, ld_u, s);
 }
 
 extern "C" int wasabi_hologram(const wasabi_lut *lut, const wasabi_point *pts, int64_t n,

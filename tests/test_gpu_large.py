@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import paper_1708_04233_amd as cgh
-from workloads import WASABI_16384, WASABI_65536, grid_points, height_field_points
+from parity import assert_field
+from workloads import WASABI_2048, WASABI_16384, WASABI_65536, grid_points, height_field_points
 
 pytestmark = pytest.mark.gpu
 
@@ -36,9 +37,8 @@ def check_windows(orc, olut, oq, u, side, B, seed, k=3):
     for x0, y0 in windows(seed, side, B, k):
         want = orc.wasabi(olut, near(oq, x0, y0, WIN, reach), x0, y0, WIN, WIN)
         got = u[y0:y0 + WIN, x0:x0 + WIN].cpu().numpy().astype(np.complex128)
-        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        err, _ = assert_field(got, want, tol=TOL, what=(x0, y0))
         worst = max(worst, err)
-        assert err <= TOL, (x0, y0, err)
     return worst
 
 
@@ -176,3 +176,24 @@ def test_65536_40db_selectivity_windows(orc, dtype):
     check_windows(orc, olut, orc.quantize(pts, olut.params), u, w["nx"], B, seed=8, k=1)
     del u
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_2048_headline_40db_windows(orc, dtype):
+    """The 2048^2 headline workload (N = 10^4, 64 planes, L = 3) at the 40 dB selectivity, whole, as
+    the benchmark times it: gamma >= 0.35 takes the dense-layout kernel, and the 1024 tiles are all
+    resident, so plane pacing is on.  The oracle's LUT (FP32 or FP16 values) is imported; two
+    corners and three seeded windows of 256^2 are checked against the oracle."""
+    w = WASABI_2048
+    g = _gamma40()
+    assert g >= 0.35
+    vt = {"f32": (orc.F32, cgh.F32), "f16": (orc.F16, cgh.F16)}[dtype]
+    kw = dict(n_depth=w["n_depth"], levels=w["levels"], gamma=g, max_window=w["max_window"])
+    olut = orc.build_lut(orc.LutParams(value_dtype=vt[0], **kw))
+    lut = cgh.wasabi_lut_import(cgh.LutParams(value_dtype=vt[1], **kw), olut.off, olut.idx, olut.val)
+    B = 1 << w["levels"]
+    pts = grid_points(w["seed"], w["n"], w["nx"], w["ny"], B, w["z_lo"], w["z_hi"])
+    q = cgh.wasabi_quantize(lut, torch.from_numpy(pts).cuda())
+    u = cgh.wasabi_hologram_fused(lut, q, 0, 0, w["nx"], w["ny"])
+    torch.cuda.synchronize()
+    check_windows(orc, olut, orc.quantize(pts, olut.params), u, w["nx"], B, seed=12)
