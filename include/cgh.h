@@ -222,6 +222,19 @@ int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *pts_dev, in
                           int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *u_dev,
                           int64_t ld_u, void *stream);
 
+/* wasabi_hologram_fused for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, result and
+ * errors as wasabi_hologram_fused; nothing is allocated and no memory is freed: the binning's
+ * scratch comes from a static device buffer of 64 MiB that the library holds on every device it
+ * runs on until the process ends (a problem needing more gives CGH_ENOMEM before any launch;
+ * enough for the 2048 x 2048, N = 10^4 workload, about 16 MiB).  Every call on a device shares
+ * that device's buffer: calls that overlap in time on one device (other streams, other threads)
+ * race and must be serialised by the caller; calls on one stream are ordered by it.  Counters in
+ * the buffer are cleared by the call's own kernels. */
+int wasabi_hologram_fused_noalloc(const wasabi_lut *lut, const wasabi_point *pts_dev, int64_t n,
+                                  int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *u_dev,
+                                  int64_t ld_u, void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Numerical propagation (the reconstruction Sec. 3 assesses holograms by) and the wavefront
  * recording plane (the conclusion's next step).

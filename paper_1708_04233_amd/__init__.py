@@ -12,6 +12,7 @@ the C ABI in ``include/cgh.h``:
   wasabi_idwt             inverse Haar transform (Sec. 2 step 3)
   wasabi_hologram         sub-hologram procedure (Sec. 2, large-scale steps 2-4)
   wasabi_hologram_fused   the same, tile by tile in on-chip memory
+  wasabi_hologram_fused_noalloc  the same without allocating (static scratch buffer)
   cgh_propagate           angular-spectrum propagation (numerical reconstruction)
   wasabi_hologram_wrp     WASABI on a wavefront recording plane, then propagation
   Server                  cgh_server_*: hologram jobs with continuous batching under a memory budget
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
         "wasabi_idwt": ([P, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram": ([P, P, I64, I64, I64, I32, I32, I32, P, I64, P], ctypes.c_int),
         "wasabi_hologram_fused": ([P, P, I64, I64, I64, I32, I32, P, I64, P], ctypes.c_int),
+        "wasabi_hologram_fused_noalloc": ([P, P, I64, I64, I64, I32, I32, P, I64, P], ctypes.c_int),
         "cgh_propagate": ([P, P, I32, I32, D, D, D, P], ctypes.c_int),
         "wasabi_hologram_wrp": ([P, P, I64, D, I32, I32, P, P], ctypes.c_int),
         "cgh_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(P)], ctypes.c_int),
@@ -335,6 +337,17 @@ def wasabi_hologram_fused(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, 
     _check(load().wasabi_hologram_fused(lut.handle, _dev(q, "points", torch.int32, (n, 4)), n, ox,
                                         oy, nx, ny, ctypes.c_void_p(u.data_ptr()), u.stride(0),
                                         _stream()))
+    return u
+
+
+def wasabi_hologram_fused_noalloc(lut: Lut, q: torch.Tensor, ox: int, oy: int, nx: int, ny: int,
+                                  u: torch.Tensor) -> torch.Tensor:
+    """wasabi_hologram_fused with the library's static scratch buffer: allocates nothing."""
+    n = q.shape[0]
+    u = _out_window(u, nx, ny, q.device)
+    _check(load().wasabi_hologram_fused_noalloc(lut.handle, _dev(q, "points", torch.int32, (n, 4)), n, ox,
+                                                oy, nx, ny, ctypes.c_void_p(u.data_ptr()), u.stride(0),
+                                                _stream()))
     return u
 
 

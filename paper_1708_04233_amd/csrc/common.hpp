@@ -171,9 +171,9 @@ int wavelet_filters(int wavelet, double *lo, double *hi);
 int coiflet_hologram(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, int64_t ox, int64_t oy,
                      int32_t nx, int32_t ny, int32_t sub, void *u, int64_t ld_u, hipStream_t s);
 
-// Upper bound (bytes) of the device scratch wasabi_hologram_fused takes from the stream-ordered
-// pool for n points on an nx x ny window at origin (0, 0).
-int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny);
+// Upper bound (bytes) of the device scratch wasabi_hologram_fused takes for n points on an nx x ny
+// window (any origin), with or without the plane-pacing counters.
+int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny, bool pacing);
 
 // wasabi_hologram_fused at origin (0, 0), u contiguous, without plane pacing (for work that shares
 // the device with other streams, where the tiles of one launch cannot count on being co-resident),

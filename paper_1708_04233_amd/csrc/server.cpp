@@ -132,7 +132,7 @@ size_t round_up(size_t b)
 size_t work_bytes_of(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny)
 {
     size_t b = round_up(sizeof(double) * 4 * (size_t)n) + round_up(sizeof(wasabi_point) * (size_t)n);
-    if (lut) b += (size_t)fused_scratch_bound(lut, n, nx, ny);
+    if (lut) b += (size_t)fused_scratch_bound(lut, n, nx, ny, false);
     return b;
 }
 

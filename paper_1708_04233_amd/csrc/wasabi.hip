@@ -1769,7 +1769,7 @@ int idwt_impl(const void *psi, int32_t nx, int32_t ny, int32_t levels, void *u, 
 
 }  // namespace
 
-int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny)
+int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_t ny, bool pacing)
 {
     TileGeom g = make_geom(0, 0, nx, ny);
     choose_lists(g);
@@ -1786,6 +1786,7 @@ int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_
     } else {
         t += scan(ntiles);
     }
+    if (pacing) t += r(4 * (int64_t)lut->n_tables * kPaceCounters);
     return t;
 }
 
@@ -1895,4 +1896,63 @@ extern "C" int wasabi_hologram_fused(const wasabi_lut *lut, const wasabi_point *
     if (lut->prm.wavelet != CGH_HAAR)
         return fail(CGH_EINVAL, "the fused path inverts Haar blocks on chip; a coiflet LUT needs wasabi_hologram");
     return superpose_impl(lut, pts, n, ox, oy, nx, ny, u, ld_u, MODE_FUSED, (hipStream_t)stream);
+}
+
+
+// ---- the fused hologram without allocation ---------------------------------------------------
+// Scratch of wasabi_hologram_fused_noalloc: a file-scope device array, one copy on every device
+// the library runs on, held until the process ends.  Host code never uses the array's name as a
+// device address (on the host it only names the symbol): the address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace cgh {
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+int static_scratch(void **out)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    CGH_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CGH_EINVAL, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return fail(CGH_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        }
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return CGH_OK;
+}
+
+}  // namespace
+}  // namespace cgh
+
+extern "C" int wasabi_hologram_fused_noalloc(const wasabi_lut *lut, const wasabi_point *pts, int64_t n,
+                                             int64_t ox, int64_t oy, int32_t nx, int32_t ny, void *u,
+                                             int64_t ld_u, void *stream)
+{
+    using namespace cgh;
+    int rc = check_common(lut, pts, n, ox, oy, nx, ny, u);
+    if (rc) return rc;
+    if (ld_u < nx) return fail(CGH_EINVAL, "ld_u < nx");
+    if (lut->prm.wavelet != CGH_HAAR)
+        return fail(CGH_EINVAL, "the fused path inverts Haar blocks on chip; a coiflet LUT needs wasabi_hologram");
+    const int64_t need = fused_scratch_bound(lut, n, nx, ny, true);
+    if (need > (int64_t)kStaticScratchBytes)
+        return fail(CGH_ENOMEM, "%lld points on a %d x %d window need %lld bytes of scratch; the static buffer holds %zu",
+                    (long long)n, nx, ny, (long long)need, kStaticScratchBytes);
+    void *buf = nullptr;
+    if ((rc = static_scratch(&buf))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s, buf, kStaticScratchBytes);
+    return superpose_impl(lut, pts, n, ox, oy, nx, ny, u, ld_u, MODE_FUSED, s, true, &sc);
 }
