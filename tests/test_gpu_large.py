@@ -148,10 +148,10 @@ def test_16384_storage_precision_vs_fp64(fp64_windows, dtype):
     assert err <= PREC_BOUND[dtype]
 
 
-def _gamma40():
-    """The 40 dB selectivity of the 2048^2 workload, written by the oracle's gamma sweep."""
+def _gamma40(workload="2048"):
+    """The 40 dB selectivity of the 2048^2 or 65536^2 workload, written by the oracle's sweep."""
     import os
-    with open(os.path.join(os.path.dirname(__file__), "golden", "gamma40_2048.txt")) as f:
+    with open(os.path.join(os.path.dirname(__file__), "golden", "gamma40_%s.txt" % workload)) as f:
         return float([ln for ln in f if ln.strip() and not ln.startswith("#")][0])
 
 
@@ -161,7 +161,7 @@ def test_65536_40db_selectivity_windows(orc, dtype):
     LUT values as the benchmark times it, on sampled windows against the oracle given the same
     (storage-rounded) LUT values."""
     w = WASABI_65536
-    g = _gamma40()
+    g = _gamma40("65536")
     assert g >= 0.35
     vt = {"f32": (orc.F32, cgh.F32), "f16": (orc.F16, cgh.F16)}[dtype]
     kw = dict(n_depth=w["n_depth"], levels=w["levels"], gamma=g, max_window=w["max_window"])
