@@ -293,6 +293,9 @@ typedef struct {
     double sim_ns_per_pixel;
     const wasabi_lut *lut;     /* shared by every job; must outlive the server (ignored when
                                   simulate = 1 and NULL is given: jobs then need multiples of 8)  */
+    uint64_t fail_ticket;      /* testing the failure path: the job with this ticket fails as its
+                                  work is being issued (after its result memory was taken), with
+                                  status CGH_EHIP; 0 = none                                       */
 } cgh_server_config;
 
 typedef struct {

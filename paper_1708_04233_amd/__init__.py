@@ -56,7 +56,7 @@ class _LutParams(ctypes.Structure):
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
                 ("simulate", ctypes.c_int32), ("sim_ns_per_pixel", ctypes.c_double),
-                ("lut", ctypes.c_void_p)]
+                ("lut", ctypes.c_void_p), ("fail_ticket", ctypes.c_uint64)]
 
 
 class _Job(ctypes.Structure):
@@ -388,10 +388,10 @@ class Server:
     the schedule on the host only (no device work; results carry no hologram)."""
 
     def __init__(self, lut: Lut | None, hbm_budget_bytes: int, max_slots: int = 2,
-                 simulate: bool = False, sim_ns_per_pixel: float = 0.0):
+                 simulate: bool = False, sim_ns_per_pixel: float = 0.0, fail_ticket: int = 0):
         self._lut = lut  # keeps the LUT alive while the server exists
         cfg = _ServerConfig(hbm_budget_bytes, max_slots, 1 if simulate else 0, sim_ns_per_pixel,
-                            lut.handle if lut is not None else None)
+                            lut.handle if lut is not None else None, fail_ticket)
         h = ctypes.c_void_p()
         _check(load().cgh_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

@@ -164,6 +164,8 @@ int issue(cgh_server *S, ServerJob &j, Slot &sl)
     }
     CGH_TRY_HIP(hipMallocAsync(&j.d_u, sizeof(float) * 2 * (size_t)j.nx * j.ny, s));
     j.result_stream = s;
+    if (j.ticket == S->cfg.fail_ticket)
+        return fail(CGH_EHIP, "job %llu: issue failed (forced by fail_ticket)", (unsigned long long)j.ticket);
     // arena: device points | quantised points | superposition scratch
     const size_t pts_bytes = round_up(bytes), q_bytes = round_up(sizeof(wasabi_point) * (size_t)j.n);
     char *ar = (char *)sl.arena;
@@ -252,6 +254,11 @@ void admit(cgh_server *S, ServerJob &j, int slot, std::unique_lock<std::mutex> &
     sl.ticket = j.ticket;
     j.t_start = j.t_admit;
     if (S->cfg.simulate) {
+        if (j.ticket == S->cfg.fail_ticket) {   // the modelled issue fails: the same path as on the device
+            j.t_done = S->now();
+            retire(S, j, fail(CGH_EHIP, "job %llu: issue failed (forced by fail_ticket)", (unsigned long long)j.ticket));
+            return;
+        }
         j.sim_end = j.t_start + S->cfg.sim_ns_per_pixel * 1e-9 * (double)j.nx * (double)j.ny;
         return;
     }

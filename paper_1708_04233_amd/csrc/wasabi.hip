@@ -96,16 +96,6 @@ __device__ inline bool footprint(const wasabi_point &p, const DepthDesc *desc, i
 }
 
 constexpr int kMaxLdsTiles = 4096;   // per-workgroup tile histograms live in LDS up to this
-constexpr int kDepthChunk = 8192;     // most points per workgroup in the plane sort
-
-// Points per workgroup of the plane sort: 8192, or fewer for small point sets so that at least
-// ~64 workgroups share the work (multiples of the 1024-thread workgroup).
-inline int64_t depth_chunk(int64_t n)
-{
-    const int64_t c = ((n + 63) / 64 + 1023) / 1024 * 1024;
-    return std::min<int64_t>(std::max<int64_t>(c, 1024), kDepthChunk);
-}
-
 // ---- point sort by (plane, row band): points grouped by plane and, within a plane, by 64-row band
 //      (invalid ones last).  Tile lists built from this order walk each plane's points by row, so
 //      at any moment the tiles read the same horizontal band of the plane's table: the table
@@ -141,60 +131,106 @@ int zero_words(void *p, int64_t n, hipStream_t s)
     return CGH_OK;
 }
 
-template <bool LDS>
-__global__ __launch_bounds__(1024) void depth_count_kernel(const wasabi_point *pts, int64_t n,
-                                                           SortKey key, int64_t chunk, int32_t *counts)
+// ---- stable radix sort (least significant digit first) -----------------------------------------
+// Each pass is a stable counting sort on `bits` bits of an integer key.  Block b takes `per`
+// consecutive items: it counts their digits into column b of a digit-major matrix, whose
+// exclusive scan gives every (digit, block) its output range; the block then writes its items in
+// input order, a round of 256 at a time: a lane's rank among the lanes of its wave with the same
+// digit comes from one ballot per key bit, the waves before it add their counts (kept in LDS per
+// wave and digit), and a running offset per digit carries the rounds.  Equal keys keep their input
+// order, so the sorted order -- and every sum taken in it later -- does not depend on timing.
+constexpr int kSortThreads = 256;   // 4 waves
+constexpr int kSortMaxBits = 12;    // digits per pass: at most 4096 (48 KiB of LDS in the scatter)
+
+struct PointKey {                   // points by (plane, row band) bin
+    using T = wasabi_point;
+    static constexpr bool kPair = false;
+    SortKey k;
+    __device__ int operator()(const wasabi_point &p) const { return sort_key(p, k); }
+};
+
+struct PairKey {                    // (list cell << 32 | point) pairs by list cell
+    using T = unsigned long long;
+    static constexpr bool kPair = true;
+    __device__ int operator()(unsigned long long v) const { return (int)(v >> 32); }
+};
+
+template <class K>
+__global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const typename K::T *in, int64_t n,
+                                                                   const int64_t *n_dev, K key, int shift,
+                                                                   int bits, int64_t per, int nblk,
+                                                                   int32_t *mat)
 {
-    extern __shared__ int hist[];  // nbins (LDS variant)
-    const int nbins = key.n_tables * key.nyb + 1;
-    if (LDS) {
-        for (int i = threadIdx.x; i < nbins; i += 1024) hist[i] = 0;
-        __syncthreads();
-    }
-    const int64_t j0 = (int64_t)blockIdx.x * chunk;
-    const int64_t j1 = min(n, j0 + chunk);
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
-        const int d = sort_key(pts[j], key);
-        if (LDS) atomicAdd(&hist[d], 1);
-        else atomicAdd(&counts[d], 1);
-    }
-    if (LDS) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < nbins; i += 1024)
-            if (hist[i]) atomicAdd(&counts[i], hist[i]);
-    }
+    extern __shared__ int hist[];
+    const int D = 1 << bits;
+    for (int i = threadIdx.x; i < D; i += kSortThreads) hist[i] = 0;
+    __syncthreads();
+    if (n_dev) n = min(n, *n_dev);
+    const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(n, j0 + per);
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) atomicAdd(&hist[(key(in[j]) >> shift) & (D - 1)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < D; i += kSortThreads) mat[(int64_t)i * nblk + blockIdx.x] = hist[i];
 }
 
-template <bool LDS>
-__global__ __launch_bounds__(1024) void depth_scatter_kernel(const wasabi_point *pts, int64_t n,
-                                                             SortKey key, int64_t chunk,
-                                                             unsigned long long *cursor,
-                                                             wasabi_point *sorted)
+// out_low: when not NULL the items' low 32 bits go there instead of the items to `out` (the last
+// pass of the pair sort writes the point indices of the lists directly).
+template <class K>
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const typename K::T *in, int64_t n,
+                                                                     const int64_t *n_dev, K key, int shift,
+                                                                     int bits, int64_t per, int nblk,
+                                                                     const int64_t *moff, typename K::T *out,
+                                                                     int32_t *out_low)
 {
-    extern __shared__ int sh[];  // LDS variant: local count[nbins] then base[nbins] (64-bit)
-    const int nbins = key.n_tables * key.nyb + 1;
-    int *cnt = sh;
-    unsigned long long *base = (unsigned long long *)(sh + ((nbins + 1) & ~1));
-    const int64_t j0 = (int64_t)blockIdx.x * chunk;
-    const int64_t j1 = min(n, j0 + chunk);
-    if (LDS) {
-        for (int i = threadIdx.x; i < nbins; i += 1024) cnt[i] = 0;
+    extern __shared__ int sh[];
+    const int D = 1 << bits;
+    int *run = sh;                                        // next output position of each digit
+    unsigned short *wcnt = (unsigned short *)(sh + D);    // [4][D]: items per wave and digit this round
+    for (int i = threadIdx.x; i < D; i += kSortThreads) {
+        run[i] = (int)moff[(int64_t)i * nblk + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) wcnt[w * D + i] = 0;
+    }
+    __syncthreads();
+    if (n_dev) n = min(n, *n_dev);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(n, j0 + per);
+    for (int64_t base = j0; base < j1; base += kSortThreads) {
+        const int64_t j = base + threadIdx.x;
+        const bool act = j < j1;
+        typename K::T v{};
+        int dg = 0;
+        if (act) {
+            v = in[j];
+            dg = (key(v) >> shift) & (D - 1);
+        }
+        // lanes of this wave with the same digit
+        unsigned long long peers = __ballot(act);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (dg >> b) & 1;
+            const unsigned long long bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const bool leader = act && (peers & below) == 0;
+        const int cnt = __popcll(peers);
+        if (leader) wcnt[wave * D + dg] = (unsigned short)cnt;
         __syncthreads();
-        for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) atomicAdd(&cnt[sort_key(pts[j], key)], 1);
-        __syncthreads();
-        for (int i = threadIdx.x; i < nbins; i += 1024) {
-            if (cnt[i]) base[i] = atomicAdd(&cursor[i], (unsigned long long)cnt[i]);
-            cnt[i] = 0;
+        if (act) {
+            int pos = run[dg] + __popcll(peers & below);
+            for (int w = 0; w < wave; ++w) pos += wcnt[w * D + dg];
+            if constexpr (K::kPair) {
+                if (out_low) out_low[pos] = (int32_t)(uint32_t)v;
+                else out[pos] = v;
+            } else {
+                out[pos] = v;
+            }
         }
         __syncthreads();
-    }
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += 1024) {
-        const wasabi_point p = pts[j];
-        const int d = sort_key(p, key);
-        unsigned long long slot;
-        if (LDS) slot = base[d] + (unsigned long long)atomicAdd(&cnt[d], 1);
-        else slot = atomicAdd(&cursor[d], 1ull);
-        sorted[slot] = p;
+        if (leader) {
+            atomicAdd(&run[dg], cnt);
+            wcnt[wave * D + dg] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -260,6 +296,33 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(const wasabi_point *pts, 
                 else slot = atomicAdd(&cursor[(int64_t)ty * g.nlx + tx], 1ull);
                 list[slot] = (int32_t)j;
             }
+}
+
+// Deterministic lists beyond kMaxLdsTiles cells: every sorted point writes its (cell, point) pairs
+// in cell order at its own offset (an exclusive scan of its cell count), and a stable sort of the
+// pairs by cell then leaves each cell's list in sorted-point order.
+__global__ __launch_bounds__(256) void point_cells_kernel(const wasabi_point *pts, int64_t n,
+                                                          const DepthDesc *desc, int n_tables, int L,
+                                                          TileGeom g, int32_t *cells)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int ty0, ty1, tx0, tx1;
+    cells[j] = footprint(pts[j], desc, n_tables, L, g, ty0, ty1, tx0, tx1) ? (ty1 - ty0) * (tx1 - tx0) : 0;
+}
+
+__global__ __launch_bounds__(256) void pair_fill_kernel(const wasabi_point *pts, int64_t n,
+                                                        const DepthDesc *desc, int n_tables, int L,
+                                                        TileGeom g, const int64_t *poff,
+                                                        unsigned long long *pairs)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int ty0, ty1, tx0, tx1;
+    if (j >= n || !footprint(pts[j], desc, n_tables, L, g, ty0, ty1, tx0, tx1)) return;
+    int64_t at = poff[j];
+    for (int ty = ty0; ty < ty1; ++ty)
+        for (int tx = tx0; tx < tx1; ++tx)
+            pairs[at++] = ((unsigned long long)(ty * g.nlx + tx) << 32) | (unsigned long long)(uint32_t)j;
 }
 
 // Ordered lists: chunk w (`cpts` consecutive sorted points) writes its per-tile counts to column w of a
@@ -1261,25 +1324,31 @@ void dense_tile_kernel(TileArgs a)
             const int my_word = tile % kPaceCounters;
             const int want = ntiles / kPaceCounters + (lane < ntiles % kPaceCounters ? 1 : 0);
             __shared__ int s_go;
+            // A plane without points in the tile's list needs neither a wait nor a barrier: it is
+            // finished as soon as the planes before it are, and only its counter moves (with
+            // hundreds of planes and a tile's points in a few dozen of them, a wait at every plane
+            // costs a memory round trip each).
             for (int d = 0; d < nd; ++d) {
                 const int64_t q0 = p0 + bnd[d], q1 = p0 + bnd[d + 1];
-                if (pacing && d >= a.pace_slack) {
-                    if (wave == 0) {
-                        const int *w = a.plane_done + (int64_t)(d - a.pace_slack) * kPaceCounters + lane;
-                        int it = 0;
-                        while (it < kPaceSpin) {
-                            const bool ok = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
-                            if (__ballot(!ok) == 0) break;
-                            __builtin_amdgcn_s_sleep(2);
-                            ++it;
+                if (q1 > q0) {
+                    if (pacing && d >= a.pace_slack) {
+                        if (wave == 0) {
+                            const int *w = a.plane_done + (int64_t)(d - a.pace_slack) * kPaceCounters + lane;
+                            int it = 0;
+                            while (it < kPaceSpin) {
+                                const bool ok = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
+                                if (__ballot(!ok) == 0) break;
+                                __builtin_amdgcn_s_sleep(2);
+                                ++it;
+                            }
+                            if (lane == 0) s_go = it < kPaceSpin;
                         }
-                        if (lane == 0) s_go = it < kPaceSpin;
+                        __syncthreads();
+                        pacing = s_go != 0;
                     }
+                    run(q0, q1);
                     __syncthreads();
-                    pacing = s_go != 0;
                 }
-                if (q1 > q0) run(q0, q1);
-                __syncthreads();
                 if (threadIdx.x == 0)
                     __hip_atomic_fetch_add(a.plane_done + (int64_t)d * kPaceCounters + my_word, 1,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1454,7 +1523,89 @@ bool use_matrix_path(int64_t n, int64_t ntiles)
     return n > 0 && ntiles <= kMaxLdsTiles && nwg * ntiles <= (INT64_C(1) << 24);
 }
 
-// Plane-sort the points and build the per-tile point lists; results live in `sc`.
+// Bits needed for the keys 0 .. count - 1.
+inline int key_bits(int64_t count)
+{
+    int b = 1;
+    while ((INT64_C(1) << b) < count) ++b;
+    return b;
+}
+
+// Passes, digit bits and blocks of a radix sort of at most n_max items with keys of kbits bits.
+// Blocks take 4096 items; for short arrays fewer, larger blocks keep the digit matrix within one
+// workgroup's scan (16384 entries).
+struct RadixPlan {
+    int passes, bits, nblk;
+    int64_t per;
+};
+
+inline RadixPlan radix_plan(int64_t n_max, int kbits)
+{
+    RadixPlan p;
+    p.passes = std::max(1, (kbits + kSortMaxBits - 1) / kSortMaxBits);
+    p.bits = (kbits + p.passes - 1) / p.passes;
+    const int64_t D = INT64_C(1) << p.bits, n = std::max<int64_t>(n_max, 1);
+    int64_t nblk = (n + 4095) / 4096;
+    if (n <= 65536) nblk = std::max<int64_t>(1, std::min<int64_t>(nblk, 16384 / D));
+    p.per = (n + nblk - 1) / nblk;
+    p.nblk = (int)((n + p.per - 1) / p.per);
+    return p;
+}
+
+inline int64_t scratch_round(int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); }
+
+// Scratch bytes a multi-block exclusive scan of `count` counts takes (none up to 16384).
+inline int64_t scan_scratch(int64_t count) { return count <= 16384 ? 0 : scratch_round(8 * ((count + 1023) / 1024)); }
+
+// Scratch bytes of radix_sort for n_max items of `item` bytes.
+inline int64_t radix_scratch(int64_t n_max, int kbits, int64_t item)
+{
+    if (n_max <= 0) return 0;
+    const RadixPlan p = radix_plan(n_max, kbits);
+    const int64_t cells = (INT64_C(1) << p.bits) * p.nblk;
+    return scratch_round(4 * cells) + scratch_round(8 * (cells + 1)) + scan_scratch(cells) +
+           std::min(p.passes - 1, 2) * scratch_round(item * n_max);
+}
+
+// Stable LSD radix sort of n items (n_max on the host; n_dev, when not NULL, the device-resident
+// count, at most n_max) by key() into `out`, or for pairs their low 32 bits into `out_low`.
+template <class K>
+int radix_sort(const typename K::T *in, int64_t n_max, const int64_t *n_dev, K key, int kbits,
+               typename K::T *out, int32_t *out_low, Scratch &sc, hipStream_t s)
+{
+    using T = typename K::T;
+    if (n_max <= 0) return CGH_OK;
+    const RadixPlan P = radix_plan(n_max, kbits);
+    const int D = 1 << P.bits;
+    const int64_t cells = (int64_t)D * P.nblk;
+    int32_t *mat;
+    int64_t *moff;
+    T *tmp[2] = {nullptr, nullptr};
+    int rc;
+    if ((rc = sc.alloc((void **)&mat, sizeof(int32_t) * cells))) return rc;
+    if ((rc = sc.alloc((void **)&moff, sizeof(int64_t) * (cells + 1)))) return rc;
+    for (int i = 0; i < std::min(P.passes - 1, 2); ++i)
+        if ((rc = sc.alloc((void **)&tmp[i], sizeof(T) * n_max))) return rc;
+    const T *src = in;
+    for (int p = 0; p < P.passes; ++p) {
+        const bool last = p == P.passes - 1;
+        T *dst = last ? out : tmp[p % 2];
+        hipLaunchKernelGGL(radix_count_kernel<K>, dim3(P.nblk), dim3(kSortThreads), sizeof(int) * D, s, src,
+                           n_max, n_dev, key, p * P.bits, P.bits, P.per, P.nblk, mat);
+        CGH_CHECK_LAUNCH("radix_count_kernel");
+        if ((rc = scan_counts(mat, cells, moff, sc, s))) return rc;
+        hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(P.nblk), dim3(kSortThreads),
+                           (sizeof(int) + 4 * sizeof(unsigned short)) * D, s, src, n_max, n_dev, key,
+                           p * P.bits, P.bits, P.per, P.nblk, moff, dst, last ? out_low : nullptr);
+        CGH_CHECK_LAUNCH("radix_scatter_kernel");
+        src = dst;
+    }
+    return CGH_OK;
+}
+
+// Plane-sort the points and build the per-tile point lists; results live in `sc`.  Every step
+// is deterministic except the list fill of the sparse layout beyond kMaxLdsTiles cells (atomic
+// cursors), whose fixed-point sums do not depend on the list order.
 int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const TileGeom &g,
                Scratch &sc, hipStream_t s, const wasabi_point **sorted_out,
                int64_t **tile_off_out, int32_t **tile_pts_out, double **bound_out, bool *ordered_out)
@@ -1466,47 +1617,21 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     key.n_tables = nd;
     key.y0 = g.oy - lut->max_span_px;
     key.nyb = sort_bands(lut, g);
-    const int nbins = nd * key.nyb + 1;
-    int32_t *counts, *dcounts;
-    int64_t *off, *doff;
-    unsigned long long *cursor, *dcursor;
+    const int64_t nbins = (int64_t)nd * key.nyb + 1;
+    int32_t *counts;
+    int64_t *off;
     int32_t *list;
     wasabi_point *sorted;
     int rc;
     if ((rc = sc.alloc((void **)&counts, sizeof(int32_t) * ntiles))) return rc;
     if ((rc = sc.alloc((void **)&off, sizeof(int64_t) * (ntiles + 1)))) return rc;
-    if ((rc = sc.alloc((void **)&cursor, sizeof(unsigned long long) * ntiles))) return rc;
     if ((rc = sc.alloc((void **)&list, sizeof(int32_t) * bound))) return rc;
-    if ((rc = sc.alloc((void **)&dcounts, sizeof(int32_t) * nbins))) return rc;
-    if ((rc = sc.alloc((void **)&doff, sizeof(int64_t) * (nbins + 1)))) return rc;
-    if ((rc = sc.alloc((void **)&dcursor, sizeof(unsigned long long) * nbins))) return rc;
     if ((rc = sc.alloc((void **)&sorted, sizeof(wasabi_point) * std::max<int64_t>(n, 1)))) return rc;
     ProfScope prof("bin", s);
-    // plane sort
-    if ((rc = zero_words(dcounts, nbins, s))) return rc;
-    const bool lds_depth = nbins <= 4096;
-    const int64_t dchunk = depth_chunk(n);
-    const unsigned dgrid = (unsigned)std::max<int64_t>((n + dchunk - 1) / dchunk, 1);
-    if (n > 0) {
-        if (lds_depth)
-            hipLaunchKernelGGL(depth_count_kernel<true>, dim3(dgrid), dim3(1024), sizeof(int) * nbins, s, pts, n, key, dchunk, dcounts);
-        else
-            hipLaunchKernelGGL(depth_count_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dchunk, dcounts);
-        CGH_CHECK_LAUNCH("depth_count_kernel");
-    }
-    // the scatter's cursors start at the offsets: written by the scan for short bin arrays
-    const bool small_bins = nbins <= 16384;
-    if ((rc = scan_counts_copy(dcounts, nbins, doff, sc, s, small_bins ? dcursor : nullptr))) return rc;
-    if (n > 0) {
-        if (!small_bins)
-            CGH_TRY_HIP(hipMemcpyAsync(dcursor, doff, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
-        const size_t sh = sizeof(int) * ((nbins + 1) & ~1) + sizeof(unsigned long long) * nbins;
-        if (lds_depth)
-            hipLaunchKernelGGL(depth_scatter_kernel<true>, dim3(dgrid), dim3(1024), sh, s, pts, n, key, dchunk, dcursor, sorted);
-        else
-            hipLaunchKernelGGL(depth_scatter_kernel<false>, dim3(dgrid), dim3(1024), 0, s, pts, n, key, dchunk, dcursor, sorted);
-        CGH_CHECK_LAUNCH("depth_scatter_kernel");
-    }
+    // plane sort: stable, by (plane, row band)
+    PointKey pk;
+    pk.k = key;
+    if ((rc = radix_sort(pts, n, nullptr, pk, key_bits(nbins), sorted, nullptr, sc, s))) return rc;
     // tile lists over the sorted points
     const int64_t nwg = (n + chunk_pts(n) - 1) / chunk_pts(n);
     const unsigned pblocks = (unsigned)((n + 255) / 256);
@@ -1535,7 +1660,27 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
             CGH_CHECK_LAUNCH("bin_count_kernel");
         }
         if ((rc = scan_counts(counts, ntiles, off, sc, s))) return rc;
-        if (n > 0) {
+        if (n > 0 && lut->dense) {
+            // the dense kernel sums in list order: the lists keep the sorted order of the points
+            if (bound > INT32_MAX) return fail(CGH_EINVAL, "more than 2^31 - 1 (list cell, point) pairs");
+            int32_t *pc;
+            int64_t *poff;
+            unsigned long long *pairs;
+            if ((rc = sc.alloc((void **)&pc, sizeof(int32_t) * n))) return rc;
+            if ((rc = sc.alloc((void **)&poff, sizeof(int64_t) * (n + 1)))) return rc;
+            if ((rc = sc.alloc((void **)&pairs, sizeof(unsigned long long) * bound))) return rc;
+            hipLaunchKernelGGL(point_cells_kernel, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, pc);
+            CGH_CHECK_LAUNCH("point_cells_kernel");
+            if ((rc = scan_counts(pc, n, poff, sc, s))) return rc;
+            hipLaunchKernelGGL(pair_fill_kernel, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, poff, pairs);
+            CGH_CHECK_LAUNCH("pair_fill_kernel");
+            if ((rc = radix_sort(pairs, bound, poff + n, PairKey(), key_bits(ntiles), (unsigned long long *)nullptr,
+                                 list, sc, s)))
+                return rc;
+            *ordered_out = true;
+        } else if (n > 0) {
+            unsigned long long *cursor;
+            if ((rc = sc.alloc((void **)&cursor, sizeof(unsigned long long) * ntiles))) return rc;
             CGH_TRY_HIP(hipMemcpyAsync(cursor, off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToDevice, s));
             if (lds_tiles)
                 hipLaunchKernelGGL(bin_fill_kernel<true>, dim3(pblocks), dim3(256), 0, s, sorted, n, lut->desc, nd, L, g, cursor, list);
@@ -1775,16 +1920,20 @@ int64_t fused_scratch_bound(const wasabi_lut *lut, int64_t n, int32_t nx, int32_
     choose_lists(g);
     const int64_t ntiles = (int64_t)g.nlx * g.nly;  // lists
     const int64_t nbins = (int64_t)lut->n_tables * sort_bands(lut, g) + 1;
-    auto r = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
-    auto scan = [&](int64_t count) { return r(8 * ((count + 1023) / 1024)); };
-    int64_t t = r(4 * ntiles) + r(8 * (ntiles + 1)) + r(8 * ntiles) + r(8 * ntiles) + r(4 * pair_bound(lut, n, g)) +
-                r(4 * nbins) + r(8 * (nbins + 1)) + r(8 * nbins) + r(16 * std::max<int64_t>(n, 1)) +
-                scan(nbins);
+    const int64_t bound = pair_bound(lut, n, g);
+    auto r = scratch_round;
+    // counts, offsets, lists, sorted points, the plane sort, the cell bounds (bin_points' order)
+    int64_t t = r(4 * ntiles) + r(8 * (ntiles + 1)) + r(4 * bound) + r(16 * std::max<int64_t>(n, 1)) +
+                radix_scratch(n, key_bits(nbins), 16) + r(8 * ntiles);
     if (use_matrix_path(n, ntiles)) {
         const int64_t cells = (n + chunk_pts(n) - 1) / chunk_pts(n) * ntiles;
-        t += r(4 * cells) + r(8 * (cells + 1)) + scan(cells);
+        t += r(4 * cells) + r(8 * (cells + 1)) + scan_scratch(cells);
     } else {
-        t += scan(ntiles);
+        t += scan_scratch(ntiles);
+        if (lut->dense)
+            t += r(4 * n) + r(8 * (n + 1)) + scan_scratch(n) + r(8 * bound) + radix_scratch(bound, key_bits(ntiles), 8);
+        else
+            t += r(8 * ntiles);
     }
     if (pacing) t += r(4 * (int64_t)lut->n_tables * kPaceCounters);
     return t;

@@ -133,3 +133,25 @@ def test_rejections_with_a_real_lut(lut16):
         with pytest.raises(cgh.CghError) as e:
             s.submit(np.zeros((10, 4)), 100, 64)
         assert e.value.code == cgh.CGH_EINVAL
+
+
+def test_forced_failure_in_a_mix(lut16):
+    """One job of a mix fails while its work is issued (forced with fail_ticket, after its result
+    memory was taken): it ends with CGH_EHIP, the other jobs' holograms are still each one's alone,
+    and the budget gets every byte back."""
+    jobs = mix(500, [1024, 2048, 1024, 2048, 1024], [3000, 8000, 2000, 6000, 4000])
+    ref = [alone(lut16, side, p) for side, p in jobs]
+    with cgh.Server(lut16, 16 << 30, max_slots=2, fail_ticket=3) as s:
+        tickets = [s.submit(p, side, side) for side, p in jobs]
+        assert tickets[2] == 3
+        for k, (t, want) in enumerate(zip(tickets, ref)):
+            r = s.wait(t, 60000)
+            if k == 2:
+                assert r["status"] == cgh.CGH_EHIP and r["u"] is None
+            else:
+                assert r["status"] == cgh.CGH_OK
+                assert rel(r["u"].clone(), want) <= TOL
+            s.release(t)
+        st = s.stats()
+        assert st["failed"] == 1 and st["completed"] == 4
+        assert st["bytes_in_use"] == st["arena_bytes"]

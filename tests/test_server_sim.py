@@ -266,3 +266,22 @@ def test_submit_from_many_threads(lib):
             s.release(t)
         st = s.stats()
         assert st["completed"] == 100 and st["bytes_in_use"] == st["arena_bytes"]
+
+
+def test_forced_issue_failure_spares_other_jobs(lib):
+    """A job whose issue fails (forced with fail_ticket) ends with CGH_EHIP holding no memory; the
+    jobs queued before and after it complete, and every byte comes back once they are released."""
+    with cgh.Server(None, 1 << 40, max_slots=2, simulate=True, sim_ns_per_pixel=NS, fail_ticket=3) as s:
+        tickets = [s.submit(pts(100), 512, 512) for _ in range(6)]
+        assert tickets[2] == 3
+        res = [s.wait(t, 5000) for t in tickets]
+        assert res[2]["status"] == cgh.CGH_EHIP and res[2]["u"] is None
+        assert all(r["status"] == cgh.CGH_OK for i, r in enumerate(res) if i != 2)
+        st = s.stats()
+        assert st["failed"] == 1 and st["completed"] == 5 and st["running"] == 0
+        # the failed job gave its result memory back at once; the others hold theirs until released
+        assert st["bytes_in_use"] == st["arena_bytes"] + 5 * result_bytes(512)
+        for t in tickets:
+            s.release(t)
+        st = s.stats()
+        assert st["bytes_in_use"] == st["arena_bytes"]
