@@ -228,6 +228,9 @@ def main():
                     help="jobs per serving run (default 200 beside the headline line, 1000 for --workload serve)")
     ap.add_argument("--cpu-windows", type=int, default=24,
                     help="512^2 windows the CPU oracle computes for the baseline of the headline line")
+    ap.add_argument("--core", action="store_true",
+                    help="headline line: only the 65536^2 runs and its direct sum (no 2048^2, serving, 512^2 or "
+                         "CPU legs), for profiling")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -604,7 +607,7 @@ def run_headline(args, torch, cgh):
     q40, ms_step, ms_traced, kern40, _ = measure(lut40, args.steps, args.warmup)
     log("65536 gamma=%.2f: %.3f ms/step (traced %.3f), kernels %s" % (g40, ms_step, ms_traced, kern40))
     psnr40 = window_psnr(q40, info40)
-    if not args.no_cpu:
+    if not args.no_cpu and not args.core:
         gpu_cpu_windows = [u[y0:y0 + 512, x0:x0 + 512].cpu().numpy().astype(np.complex128)
                            for x0, y0 in [(int(v[0]) * B, int(v[1]) * B) for v in
                                           np.random.default_rng(17).integers(0, (nx - 512) // B, (args.cpu_windows, 2))]]
@@ -667,22 +670,27 @@ def run_headline(args, torch, cgh):
     torch.cuda.empty_cache()
 
     # ---- the 2048^2 workload, serving, the 512^2 direct sum ------------------------------------
-    w2048 = run_2048(args, torch, cgh, full=False)
-    log("2048", w2048)
-    slut = serve_lut(cgh)
-    serving_runs, solo = [], None
-    for budget in (64 << 30, 4 << 30):
-        for rho in (0.5, 0.8, 0.95):
-            r = serve_run(torch, cgh, slut, args.serve_jobs or 200, 10, rho, budget, 3, solo=solo)
-            solo = r["solo_jobs_per_s"]
-            serving_runs.append(r)
-            log("serve", rho, budget >> 30, "GB:", r["p50_ms"], r["p99_ms"])
-    del slut
-    d512 = direct_512(torch, cgh, args.steps)
+    w2048, serving, d512 = None, None, None
+    if not args.core:
+        w2048 = run_2048(args, torch, cgh, full=False)
+        log("2048", w2048)
+        slut = serve_lut(cgh)
+        serving_runs, solo = [], None
+        for budget in (64 << 30, 4 << 30):
+            for rho in (0.5, 0.8, 0.95):
+                r = serve_run(torch, cgh, slut, args.serve_jobs or 200, 10, rho, budget, 3, solo=solo)
+                solo = r["solo_jobs_per_s"]
+                serving_runs.append(r)
+                log("serve", rho, budget >> 30, "GB:", r["p50_ms"], r["p99_ms"])
+        del slut
+        serving = {"slots": 3, "jobs_per_run": args.serve_jobs or 200, "runs": serving_runs,
+                   "p50_ms": serving_runs[1]["p50_ms"], "p99_ms": serving_runs[1]["p99_ms"],
+                   "lut": serving_runs[0]["lut"]}
+        d512 = direct_512(torch, cgh, args.steps)
 
     # ---- CPU baseline: the oracle on sampled windows, on the host's cores ---------------------
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not args.core:
         nproc, model = cpu_info()
         threads = max(1, min(16, nproc or 1, args.cpu_windows))
         cwins = [(int(v[0]) * B, int(v[1]) * B) for v in
@@ -723,9 +731,7 @@ def run_headline(args, torch, cgh):
            "roofline": roofline,
            "cpu_baseline": cpu,
            "wasabi_2048": w2048,
-           "serving": {"slots": 3, "jobs_per_run": args.serve_jobs or 200, "runs": serving_runs,
-                       "p50_ms": serving_runs[1]["p50_ms"], "p99_ms": serving_runs[1]["p99_ms"],
-                       "lut": serving_runs[0]["lut"]},
+           "serving": serving,
            "direct_512": d512,
            "hbm_copy_GBps": hbm_copy,
            "paper_context": "paper: ~354 s for a 65536^2 hologram of 95,949 points on one CPU"}
