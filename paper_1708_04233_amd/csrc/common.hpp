@@ -151,6 +151,10 @@ struct wasabi_lut {
     int32_t *blk_off;                 // device
     void *values;                     // device: float2 (F32) or uint32 packed pair (F16, BF16)
     uint16_t *keys;                   // device
+    int32_t *wkeys;                   // device, sparse layout only: each entry's byte offset in the
+                                      // superposition's on-chip tile buffer, (table block row * row
+                                      // stride + key) * 8, for a table whose block (0, 0) sits on
+                                      // tile block (0, 0)
     bool dense;                       // dense layout present (used by the superposition)
     void *dense_values;               // device, same element type as values
     int64_t dense_zero;               // first of kDenseZero zero values after the dense tables

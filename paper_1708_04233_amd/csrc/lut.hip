@@ -463,6 +463,19 @@ __global__ __launch_bounds__(256) void dense_scatter_kernel(const DenseJob *jobs
     }
 }
 
+// ---- sparse layout: every entry's byte offset in the tile buffer (one workgroup per table) -------
+__global__ __launch_bounds__(256) void wide_key_kernel(const DepthDesc *desc, const int32_t *blk_off,
+                                                       const uint16_t *keys, int row_words, int32_t *wkeys)
+{
+    const DepthDesc d = desc[blockIdx.x];
+    const int32_t *bo = blk_off + d.blkoff_base;
+    for (int br = 0; br < d.nb; ++br) {
+        const int32_t e0 = bo[(int64_t)br * d.nb], e1 = bo[(int64_t)(br + 1) * d.nb];
+        for (int32_t e = e0 + threadIdx.x; e < e1; e += 256)
+            wkeys[d.entry_base + e] = (br * row_words + (int)keys[d.entry_base + e]) * 8;
+    }
+}
+
 // ---- quantisation ---------------------------------------------------------------------------
 // z_shift: subtracted from every depth first (0, or a wavefront recording plane's distance).
 __global__ void quantize_kernel(const double4 *pts, int64_t n, double pitch, double z_min,
@@ -656,6 +669,24 @@ int finish_lut(wasabi_lut *lut, const std::vector<int32_t> &blk_off_host)
     int rc = build_dense(lut, blk_off_host);
     if (rc) return rc;
     CGH_TRY_HIP(hipMemcpy(lut->desc, lut->desc_host.data(), sizeof(DepthDesc) * n, hipMemcpyHostToDevice));
+    if (!lut->dense) {
+        // the sparse superposition's tile buffer: 64 >> L blocks of block_stride(L) words per block row,
+        // plus the row pad
+        const int L = lut->L, row_words = (64 >> L) * block_stride(L) + row_pad(L);
+        const int32_t wmax = *std::max_element(lut->W.begin(), lut->W.end());
+        if ((int64_t)(wmax / lut->B) * row_words * 8 >= INT32_MAX)
+            return fail(CGH_EINVAL, "table too large for the sparse layout's offsets");
+        const size_t wb = sizeof(int32_t) * (size_t)std::max<int64_t>(lut->total_entries, 1);
+        if (hipMalloc((void **)&lut->wkeys, wb) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CGH_ENOMEM, "sparse LUT offsets (%zu bytes)", wb);
+        }
+        lut->device_bytes += wb;
+        hipLaunchKernelGGL(wide_key_kernel, dim3(n), dim3(256), 0, 0, lut->desc, lut->blk_off, lut->keys, row_words,
+                           lut->wkeys);
+        CGH_TRY_HIP(hipGetLastError());
+        CGH_TRY_HIP(hipDeviceSynchronize());
+    }
     return CGH_OK;
 }
 
@@ -708,6 +739,7 @@ wasabi_lut *new_lut(const wasabi_lut_params *prm)
     lut->blk_off = nullptr;
     lut->values = nullptr;
     lut->keys = nullptr;
+    lut->wkeys = nullptr;
     lut->dense = false;
     lut->dense_zero = 0;
     lut->dense_values = nullptr;
@@ -1041,6 +1073,7 @@ extern "C" void wasabi_lut_free(wasabi_lut *lut)
     (void)hipFree(lut->blk_off);
     (void)hipFree(lut->values);
     (void)hipFree(lut->keys);
+    (void)hipFree(lut->wkeys);
     (void)hipFree(lut->dense_values);
     (void)hipFree(lut->dense_rows);
     delete lut;

@@ -494,6 +494,7 @@ struct TileArgs {
     const int32_t *blk_off;
     const void *values;
     const uint16_t *keys;
+    const int32_t *wkeys;      // sparse layout: each entry's byte offset in the tile buffer (L >= 3)
     const wasabi_point *pts;
     const int64_t *tile_off;
     const int32_t *tile_pts;
@@ -829,15 +830,15 @@ template <int L>
 struct PairStep {
     using S = TileShape<L>;
     int ex[S::TB], off[S::TB];
-    int total, dst0b;       // dst0b: the LDS byte address of the pair's word 0
+    int total, baseb;       // baseb: LDS byte address of the table's block (0, 0) in this tile
     const char *vals;       // the plane's first stored value
-    const uint16_t *keys;   // and key
+    const int32_t *wkeys;   // and the byte offset of its first entry
     double sa;
 };
 
 template <int L, int VT>
 __device__ inline void pair_setup(PairStep<L> &P, int k, const int *m_rs, const int *m_rcp, int m_eb,
-                                  int m_dst0, float m_amp, int shift, const TileArgs &a)
+                                  int m_base, float m_amp, int shift, const TileArgs &a)
 {
     using S = TileShape<L>;
     constexpr int vbytes = VT == CGH_F32 ? 8 : 4;
@@ -851,32 +852,31 @@ __device__ inline void pair_setup(PairStep<L> &P, int k, const int *m_rs, const 
     }
     const int eb = __builtin_amdgcn_readlane(m_eb, k);
     P.vals = (const char *)a.values + (int64_t)eb * vbytes;
-    P.keys = a.keys + eb;
-    P.dst0b = __builtin_amdgcn_readlane(m_dst0, k) * (int)sizeof(unsigned long long);
+    P.wkeys = a.wkeys + eb;
+    P.baseb = __builtin_amdgcn_readlane(m_base, k) * (int)sizeof(unsigned long long);
     P.sa = ldexp((double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_amp), k)), shift);
 }
 
-// The row of entry e: a select chain over rows R, R + 1, ... (indices fixed at compile time, so
-// that the rows' values stay in registers rather than in an indexed private array).
+// The entry offset of the row holding entry e: a select chain over rows R, R + 1, ... (indices
+// fixed at compile time, so that the rows' values stay in registers rather than in an indexed
+// private array).
 template <int L, int R>
-__device__ inline void row_select(const PairStep<L> &P, int e, int &o, int &drowb)
+__device__ inline void row_select(const PairStep<L> &P, int e, int &o)
 {
     if constexpr (R < TileShape<L>::TB) {
-        if (e >= P.ex[R]) {
-            o = P.off[R];
-            drowb = R * TileShape<L>::ROW * (int)sizeof(unsigned long long);
-        }
-        row_select<L, R + 1>(P, e, o, drowb);
+        if (e >= P.ex[R]) o = P.off[R];
+        row_select<L, R + 1>(P, e, o);
     }
 }
 
-// Entry e of the pair (0 <= e < total): its stored value, and the byte address of its LDS word.
+// Entry e of the pair (0 <= e < total): its stored value, and the byte address of its LDS word
+// (the entry's own offset from the table's block (0, 0), which carries its block row, plus where
+// that block sits in the tile).
 template <int L, int VT>
 __device__ inline void pair_entry(const PairStep<L> &P, int e, float2 &v, int &wbyte)
 {
-    using S = TileShape<L>;
-    int o = P.off[0], drowb = 0;
-    row_select<L, 1>(P, e, o, drowb);
+    int o = P.off[0];
+    row_select<L, 1>(P, e, o);
     const uint32_t rel = (uint32_t)(e + o);  // entry index within the plane's table
     if constexpr (VT == CGH_F32) {
         v = *reinterpret_cast<const float2 *>(P.vals + (rel << 3));
@@ -892,9 +892,7 @@ __device__ inline void pair_entry(const PairStep<L> &P, int e, float2 &v, int &w
             v = make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
         }
     }
-    wbyte = P.dst0b + drowb +
-            (int)*reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(P.keys) + (rel << 1)) *
-                (int)sizeof(unsigned long long);
+    wbyte = P.baseb + *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(P.wkeys) + (rel << 2));
 }
 
 __device__ inline void lds_add(unsigned long long *acc, int wbyte, unsigned long long v)
@@ -904,7 +902,7 @@ __device__ inline void lds_add(unsigned long long *acc, int wbyte, unsigned long
 
 template <int L, int VT>
 __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, int cnt, int m_nrows,
-                                  int m_bo, int m_nb, int m_bc0, int m_bc1, int m_eb, int m_dst0,
+                                  int m_bo, int m_nb, int m_bc0, int m_bc1, int m_eb, int m_base,
                                   float m_amp, int shift)
 {
     using S = TileShape<L>;
@@ -934,7 +932,7 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
     };
     for (int k = next_pair(0); k < cnt; k = next_pair(k + 1)) {
         PairStep<L> P;
-        pair_setup<L, VT>(P, k, m_rs, m_rcp, m_eb, m_dst0, m_amp, shift, a);
+        pair_setup<L, VT>(P, k, m_rs, m_rcp, m_eb, m_base, m_amp, shift, a);
         int c = 0;
         for (; P.total - c > 64; c += 128) {
             const int e0 = c + lane, e1 = e0 + 64;  // e0 < total
@@ -964,14 +962,17 @@ __device__ inline float2 fixed_value(unsigned long long w, int e2)
     return make_float2(ldexpf((float)re, e2), ldexpf((float)im, e2));
 }
 
-// One 2D inverse Haar step for one output of a quadruple: the output at row parity a, column parity
-// b of the next finer level.  Same operations, in the same order, as the in-LDS inverse.
+// One 2D inverse Haar step for one output of a quadruple, without the factor 1/2: the output at row
+// parity a, column parity b of the next finer level, for inputs that carry the halvings of every
+// level they still pass through (a level-l coefficient pre-scaled by 2^-l).  Scaling by powers of
+// two is exact, so this gives bit for bit the values of the halving step applied level by level,
+// with the same additions in the same order as the in-LDS inverse.
 __device__ inline float2 haar_up(float2 s, float2 h, float2 v, float2 d, int a, int b)
 {
     const float hr = b ? -h.x : h.x, hi = b ? -h.y : h.y;
     const float vr = a ? -v.x : v.x, vi = a ? -v.y : v.y;
     const float dr = (a ^ b) ? -d.x : d.x, di = (a ^ b) ? -d.y : d.y;
-    return make_float2((s.x + hr + vr + dr) * 0.5f, (s.y + hi + vi + di) * 0.5f);
+    return make_float2(s.x + hr + vr + dr, s.y + hi + vi + di);
 }
 
 // Inverse Haar of the tile from its fixed-point words.  The coarse quarter of every block (levels
@@ -988,9 +989,13 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, int e2, floa
     constexpr int B = S::B, H1 = B / 2, QT = kT / 2;   // level-1 band extent in a block / tile
     float2 *f = reinterpret_cast<float2 *>(acc);
     auto word = [](int blk, int m, int n) { return (blk / S::TB) * S::ROW + (blk % S::TB) * S::BS + m * B + n; };
+    // the coarse quarter in FP32, each coefficient pre-scaled by 2^-l for its level l (l = L for the
+    // scaling coefficient, L - floor(log2 max(m, n)) for a detail coefficient at (m, n))
     for (int i = threadIdx.x; i < QT * QT; i += NT) {
-        const int at = word(i / (H1 * H1), (i % (H1 * H1)) / H1, i % H1);
-        f[at] = fixed_value(acc[at], e2);
+        const int m = (i % (H1 * H1)) / H1, n = i % H1, mx = max(m, n);
+        const int lev = mx == 0 ? L : L - (31 - __clz(mx));
+        const int at = word(i / (H1 * H1), m, n);
+        f[at] = fixed_value(acc[at], e2 - lev);
     }
     __syncthreads();
 #pragma unroll
@@ -1034,9 +1039,9 @@ __device__ inline void fixed_inverse_store(unsigned long long *acc, int e2, floa
         if (br >= (th >> L) || bc >= (tw >> L)) continue;
         const int blk = br * S::TB + bc;
         const float2 S1 = f[word(blk, m, n)];
-        const float2 H = fixed_value(acc[word(blk, m, H1 + n)], e2);
-        const float2 V = fixed_value(acc[word(blk, H1 + m, n)], e2);
-        const float2 D = fixed_value(acc[word(blk, H1 + m, H1 + n)], e2);
+        const float2 H = fixed_value(acc[word(blk, m, H1 + n)], e2 - 1);
+        const float2 V = fixed_value(acc[word(blk, H1 + m, n)], e2 - 1);
+        const float2 D = fixed_value(acc[word(blk, H1 + m, H1 + n)], e2 - 1);
         float2 *o = out + ((int64_t)ty * kT + 2 * qm) * ld + (int64_t)tx * kT + 2 * qn;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -1139,7 +1144,8 @@ void tile_kernel(TileArgs a)
                 m_bc0 = bc0;
                 m_bc1 = bc1;
                 m_eb = (int)dd.entry_base;
-                m_dst0 = (br0 + obr) * S::ROW + obc * S::BS;
+                // L >= 3: the LDS word of the table's block (0, 0); L <= 2: of the pair's first block
+                m_dst0 = S::TB <= 8 ? obr * S::ROW + obc * S::BS : (br0 + obr) * S::ROW + obc * S::BS;
                 m_amp = pt.a;
             }
         }
@@ -1758,6 +1764,7 @@ TileArgs make_args(const wasabi_lut *lut, const wasabi_point *pts, const int64_t
     a.blk_off = lut ? lut->blk_off : nullptr;
     a.values = lut ? lut->values : nullptr;
     a.keys = lut ? lut->keys : nullptr;
+    a.wkeys = lut ? lut->wkeys : nullptr;
     a.pts = pts;
     a.tile_off = tile_off;
     a.tile_pts = tile_pts;
