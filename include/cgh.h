@@ -271,11 +271,11 @@ int wasabi_hologram_wrp(const wasabi_lut *lut, const double *pts_dev, int64_t n,
  * ny x nx complex64 hologram owned by the server.  Up to max_slots jobs run at once, each on a
  * stream of its own, so the work of different jobs overlaps on the device; a job is admitted
  * (strictly in submission order) as soon as a slot is free and its memory fits the budget, also
- * while others run.  The budget counts the device memory the server holds: each job's result
- * (8 nx ny bytes, held until cgh_server_release) and each slot's arena, which holds the working
- * memory of the job running in it (device points, quantised points, the superposition's scratch),
- * is kept for the slot's next job, grows for a larger one and is given back when an idle slot's
- * share is needed to admit a job.  The LUT is not counted.
+ * while others run.  The budget counts the device memory the jobs hold: the shared LUT (charged
+ * once, at creation), each job's result (8 nx ny bytes, held until cgh_server_release) and each
+ * slot's arena, which holds the working memory of the job running in it (device points,
+ * quantised points, the superposition's scratch), is kept for the slot's next job, grows for a
+ * larger one and is given back when an idle slot's share is needed to admit a job.
  * A scheduler thread owned by the server issues the work; the calls below are thread-safe.
  * Each slot is a stream: keep max_slots + the caller's own streams within the device's hardware
  * queues per process (GPU_MAX_HW_QUEUES, 4 by default), or enqueue calls start to wait on each
@@ -322,10 +322,12 @@ typedef struct {
     int64_t max_running;                            /* most jobs running at once so far           */
     size_t bytes_in_use, peak_bytes;                /* budgeted bytes now / at most so far        */
     size_t arena_bytes;                             /* of bytes_in_use: the slots' arenas         */
+    size_t lut_bytes;                               /* of bytes_in_use: the shared LUT            */
 } cgh_server_stats;
 
 /* Create a server on the current device (the LUT's).  Errors: CGH_EINVAL (NULL arguments, budget 0,
- * max_slots out of range, LUT on another device), CGH_EHIP. */
+ * max_slots out of range, LUT on another device), CGH_ENOMEM (the LUT alone fills the budget),
+ * CGH_EHIP. */
 int cgh_server_create(const cgh_server_config *cfg, cgh_server **out);
 
 /* Queue a job; *ticket identifies it (> 0).  Errors: CGH_EINVAL (bad sizes, NULL points with

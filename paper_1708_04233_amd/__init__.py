@@ -76,7 +76,8 @@ class _Stats(ctypes.Structure):
                 ("canceled", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
                 ("max_running", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t),
-                ("peak_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t)]
+                ("peak_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t),
+                ("lut_bytes", ctypes.c_size_t)]
 
 
 _lib = None

@@ -8,8 +8,8 @@
 // Memory: each slot keeps a device arena that holds a job's working memory (points, quantised
 // points, the superposition's scratch), grown when a larger job comes and given back when an idle
 // slot's arena is needed to admit a job; the result is allocated per job and stays charged to the
-// budget until the caller releases it.  The budget counts the arenas plus the held results, i.e.
-// the device memory the server holds.  Client calls (submit / wait / cancel / release / query)
+// budget until the caller releases it.  The budget counts the shared LUT, the arenas and the held
+// results, i.e. the device memory the server's jobs hold.  Client calls (submit / wait / cancel / release / query)
 // only touch host state under the server's mutex, except release, which frees the result.
 #include <algorithm>
 #include <chrono>
@@ -76,7 +76,8 @@ struct cgh_server {
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, std::unique_ptr<cgh::ServerJob>> jobs;
     std::vector<cgh::Slot> slots;
-    size_t used = 0;
+    size_t used = 0;        // budgeted bytes: the LUT, the slots' arenas, the held results
+    size_t lut_bytes = 0;
     cgh_server_stats st{};
     uint64_t next_ticket = 1;
     bool closing = false, stopped = false;
@@ -368,8 +369,15 @@ extern "C" int cgh_server_create(const cgh_server_config *cfg, cgh_server **out)
     if (!cfg->simulate && !cfg->lut) return fail(CGH_EINVAL, "lut is NULL");
     if (cfg->lut && cfg->lut->prm.wavelet != CGH_HAAR)
         return fail(CGH_EINVAL, "the server computes jobs on the fused path, which needs a Haar LUT");
+    // the shared LUT is device memory the server's jobs hold too: charged to the budget once
+    const size_t lut_bytes = cfg->lut ? cfg->lut->device_bytes : 0;
+    if (lut_bytes >= cfg->hbm_budget_bytes)
+        return fail(CGH_ENOMEM, "the LUT alone (%zu bytes) fills the budget of %zu", lut_bytes, cfg->hbm_budget_bytes);
     std::unique_ptr<cgh_server> S(new cgh_server);
     S->cfg = *cfg;
+    S->lut_bytes = lut_bytes;
+    S->used = lut_bytes;
+    S->st.peak_bytes = lut_bytes;
     S->t0 = Clock::now();
     S->B = cfg->lut ? cfg->lut->B : 8;
     S->slots.resize(cfg->max_slots);
@@ -416,9 +424,9 @@ extern "C" int cgh_server_submit(cgh_server *S, const cgh_job *job, uint64_t *ti
     j->ny = job->ny;
     j->result_bytes = sizeof(float) * 2 * (size_t)job->nx * job->ny;
     j->work_bytes = work_bytes_of(S->cfg.lut, job->n, job->nx, job->ny);
-    if (j->work_bytes + j->result_bytes > S->cfg.hbm_budget_bytes)
-        return fail(CGH_ENOMEM, "job needs %zu bytes, budget is %zu", j->work_bytes + j->result_bytes,
-                    S->cfg.hbm_budget_bytes);
+    if (j->work_bytes + j->result_bytes > S->cfg.hbm_budget_bytes - S->lut_bytes)
+        return fail(CGH_ENOMEM, "job needs %zu bytes, budget is %zu of which the LUT holds %zu",
+                    j->work_bytes + j->result_bytes, S->cfg.hbm_budget_bytes, S->lut_bytes);
     if (job->n > 0 && !S->cfg.simulate) {
         try {
             j->host.assign(job->host_pts, job->host_pts + 4 * job->n);
@@ -523,6 +531,7 @@ extern "C" int cgh_server_query(cgh_server *S, cgh_server_stats *out)
     out->bytes_in_use = S->used;
     out->arena_bytes = 0;
     for (const Slot &sl : S->slots) out->arena_bytes += sl.arena_cap;
+    out->lut_bytes = S->lut_bytes;
     return CGH_OK;
 }
 

@@ -63,7 +63,8 @@ def test_mix_equals_alone(request, which):
     out, st = run_mix(lut, jobs, 64 << 30, 2)
     assert st["completed"] == len(jobs) and st["failed"] == 0
     assert st["max_running"] == 2          # jobs overlapped on the device
-    assert st["bytes_in_use"] == st["arena_bytes"]   # results released; the slots keep arenas
+    # results released; the slots keep their arenas and the LUT stays charged
+    assert st["bytes_in_use"] == st["arena_bytes"] + st["lut_bytes"] and st["lut_bytes"] > 0
     for (r, u), want, (side, p) in zip(out, ref, jobs):
         if len(p) == 0:
             assert torch.count_nonzero(u).item() == 0
@@ -74,13 +75,19 @@ def test_mix_equals_alone(request, which):
 
 
 def job_bytes(lut, side, pts):
-    """Bytes the server charges for one job: its peak alone on an otherwise idle server."""
+    """Bytes the server charges for one job: its peak alone on an otherwise idle server, less the
+    LUT (charged once per server)."""
     with cgh.Server(lut, 1 << 40, max_slots=1) as s:
         t = s.submit(pts, side, side)
         s.wait(t, 60000)
-        b = s.stats()["peak_bytes"]
+        st = s.stats()
+        b = st["peak_bytes"] - st["lut_bytes"]
         s.release(t)
     return b
+
+
+def lut_bytes(lut):
+    return lut.info()["device_bytes"]
 
 
 def test_tight_budget_admission(lut16):
@@ -89,7 +96,7 @@ def test_tight_budget_admission(lut16):
     jobs = mix(300, [2048, 1024, 2048, 1024, 2048], [8000, 4000, 3000, 9000, 500])
     ref = [alone(lut16, side, p) for side, p in jobs]
     need = [job_bytes(lut16, side, p) for side, p in jobs]
-    budget = max(need)
+    budget = max(need) + lut_bytes(lut16)
     out, st = run_mix(lut16, jobs, budget, 2)
     assert st["peak_bytes"] <= budget
     for i in range(len(jobs)):
@@ -126,7 +133,10 @@ def test_small_job_matches_oracle(orc):
 
 
 def test_rejections_with_a_real_lut(lut16):
-    with cgh.Server(lut16, 8 * 1024 * 1024, max_slots=2) as s:   # 8 MB: a 1024^2 result alone
+    with pytest.raises(cgh.CghError) as e:                       # the LUT alone fills the budget
+        cgh.Server(lut16, lut_bytes(lut16), max_slots=2)
+    assert e.value.code == cgh.CGH_ENOMEM
+    with cgh.Server(lut16, lut_bytes(lut16) + 8 * 1024 * 1024, max_slots=2) as s:   # 8 MB: a 1024^2 result alone
         with pytest.raises(cgh.CghError) as e:
             s.submit(np.zeros((10, 4)), 1024, 1024)
         assert e.value.code == cgh.CGH_ENOMEM
@@ -154,4 +164,4 @@ def test_forced_failure_in_a_mix(lut16):
             s.release(t)
         st = s.stats()
         assert st["failed"] == 1 and st["completed"] == 4
-        assert st["bytes_in_use"] == st["arena_bytes"]
+        assert st["bytes_in_use"] == st["arena_bytes"] + st["lut_bytes"]
