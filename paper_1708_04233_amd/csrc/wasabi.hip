@@ -141,6 +141,7 @@ int zero_words(void *p, int64_t n, hipStream_t s)
 // order, so the sorted order -- and every sum taken in it later -- does not depend on timing.
 constexpr int kSortThreads = 256;   // 4 waves
 constexpr int kSortMaxBits = 12;    // digits per pass: at most 4096 (48 KiB of LDS in the scatter)
+constexpr int kSortPrefetch = 8;    // rounds whose items a scatter thread loads at once
 
 struct PointKey {                   // points by (plane, row band) bin
     using T = wasabi_point;
@@ -195,13 +196,26 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const typen
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(n, j0 + per);
+    // the items of kSortPrefetch rounds are loaded at once, so the rounds wait on memory once
+    typename K::T pre[kSortPrefetch];
     for (int64_t base = j0; base < j1; base += kSortThreads) {
+        const int r = (int)(((base - j0) / kSortThreads) % kSortPrefetch);
+        if (r == 0) {
+#pragma unroll
+            for (int q = 0; q < kSortPrefetch; ++q) {
+                const int64_t jq = base + (int64_t)q * kSortThreads + threadIdx.x;
+                if (jq < j1) pre[q] = in[jq];
+            }
+        }
         const int64_t j = base + threadIdx.x;
         const bool act = j < j1;
         typename K::T v{};
         int dg = 0;
         if (act) {
-            v = in[j];
+            // the round's item, picked from the prefetched ones with indices fixed at compile time
+#pragma unroll
+            for (int q = 0; q < kSortPrefetch; ++q)
+                if (q == r) v = pre[q];
             dg = (key(v) >> shift) & (D - 1);
         }
         // lanes of this wave with the same digit
@@ -1511,6 +1525,19 @@ int sort_bands(const wasabi_lut *lut, const TileGeom &g)
     const int nd = lut->n_tables;
     int nyb = (int)std::min<int64_t>(((int64_t)g.ny + 2 * lut->max_span_px + 63) / 64, 4096);
     if ((int64_t)nyb * nd + 1 > (INT64_C(1) << 26)) nyb = std::max(1, (1 << 26) / nd - 1);
+    // The bands only order a plane's points for locality (points beyond the last band join it), so
+    // a few fewer of them are harmless; when that keeps the bin count within a power of two, the
+    // radix sort may need a pass less (64 planes x 64 bands + 1 = 4097 bins -> 63 bands, 12 bits).
+    for (int b = 8; b <= 26; ++b) {
+        const int64_t cap = INT64_C(1) << b;
+        if ((int64_t)nyb * nd + 1 > cap) {
+            const int64_t fit = (cap - 1) / nd;
+            if (fit >= 1 && fit >= nyb - nyb / 16) {
+                nyb = (int)fit;
+                break;
+            }
+        }
+    }
     return nyb;
 }
 
