@@ -85,7 +85,7 @@ int cgh_direct(const double *pts_dev, int64_t n, int32_t nx, int32_t ny, int64_t
  * transform are computed in FP64; the ranking key is the strength |c|^2, computed in FP64 and
  * rounded to FP32, and equal keys go to the lower flat table index (row * W_d + col), so the kept
  * set is unique: any implementation of this rule keeps the same coefficients.  The LUT needs fewer
- * than 2^31 kept coefficients and fewer than 2^31 Haar blocks over all tables (else CGH_EINVAL,
+ * than 2^31 kept coefficients and fewer than 2^30 Haar blocks over all tables (else CGH_EINVAL,
  * returned before anything is allocated).
  * Phase tables (phases = 1): Eq.(2) moves a table by whole 2^L blocks, so a plane's single table
  * places only points on the 2^L grid.  With phase tables every plane gets 4^L tables, one per

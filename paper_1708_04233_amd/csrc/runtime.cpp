@@ -137,8 +137,8 @@ int lut_geometry(wasabi_lut *lut)
     lut->P = p.phases ? 1 << (2 * p.levels) : 1;
     lut->n_tables = n * lut->P;
     const int P = lut->P, nt = lut->n_tables;
-    // The superposition addresses entries and per-block offsets with 32-bit integers: both totals
-    // are bounded here, before anything is allocated.
+    // The superposition addresses entries with 32-bit integers and per-block offsets with 32-bit byte
+    // offsets: both totals are bounded here, before anything is allocated.
     int64_t blk_total = 0, entries = 0;
     lut->z.resize(nt);
     lut->R.resize(nt);
@@ -172,8 +172,8 @@ int lut_geometry(wasabi_lut *lut)
         }
         blk_total += (int64_t)P * ((W / B) * (W / B) + 1);
         entries += (int64_t)P * nr;
-        if (blk_total >= INT32_MAX)
-            return fail(CGH_EINVAL, "LUT of more than 2^31 - 1 Haar blocks (%d tables of up to %lld^2 pixels)", nt,
+        if (blk_total >= (INT64_C(1) << 30))
+            return fail(CGH_EINVAL, "LUT of 2^30 or more Haar blocks (%d tables of up to %lld^2 pixels)", nt,
                         (long long)W);
         if (entries >= INT32_MAX)
             return fail(CGH_EINVAL, "LUT of more than 2^31 - 1 kept coefficients");

@@ -769,10 +769,9 @@ __device__ inline void tile_inverse_and_store(float *sre, float *sim, float2 *ou
 // scaled partial and final sum stays below 2^31 in magnitude.  Rounding uses the FP64 "magic
 // number" 1.5 * 2^52: for |y| < 2^31 the low 32 bits of y + 1.5 * 2^52 are round-to-nearest-even(y)
 // in two's complement.
-// The real and imaginary parts share one 64-bit word, re * 2^32 + im (im sign-extended), added
-// with a single 64-bit atomic: 64-bit modular addition keeps the sum of the words equal to
-// (sum re) * 2^32 + (sum im) exactly, and since |sum im| < 2^31 the low 32 bits give sum im and
-// (word - sum im) / 2^32 gives sum re.
+// A coefficient's 8-byte LDS slot holds its real sum in the low 32 bits and its imaginary sum in
+// the high 32 bits, each added with its own 32-bit atomic (measured as fast as packing both parts
+// into one 64-bit add, and it needs no unpacking of the sums).
 constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
 
 __device__ inline int to_fixed(float v, double scaled_amp)
@@ -780,12 +779,12 @@ __device__ inline int to_fixed(float v, double scaled_amp)
     return __double2loint(fma((double)v, scaled_amp, kMagic));
 }
 
-__device__ inline unsigned long long packed_fixed(float2 v, double scaled_amp)
+// Adds a_j * v (scaled_amp = a_j 2^s) to the slot at byte address wbyte of the tile buffer.
+__device__ inline void lds_add(unsigned long long *acc, int wbyte, float2 v, double scaled_amp)
 {
-    const int re = to_fixed(v.x, scaled_amp), im = to_fixed(v.y, scaled_amp);
-    // re * 2^32 + im (im sign-extended): the high word is re - 1 when im < 0
-    const unsigned hi = (unsigned)re + (unsigned)(im >> 31);
-    return ((unsigned long long)hi << 32) | (unsigned)im;
+    unsigned *w = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(acc) + wbyte);
+    atomicAdd(w, (unsigned)to_fixed(v.x, scaled_amp));
+    atomicAdd(w + 1, (unsigned)to_fixed(v.y, scaled_amp));
 }
 
 // Adds the kept coefficients of one (tile, point) pair into the tile's LDS accumulators, for L <= 2
@@ -822,10 +821,7 @@ __device__ inline void add_pair(unsigned long long *acc, const void *values, con
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int e = c + 64 * u + lane;
-                if (e < rc) {
-                    const int at = d + k[u];
-                    atomicAdd(&acc[at], packed_fixed(v[u], scaled_amp));
-                }
+                if (e < rc) lds_add(acc, (d + k[u]) * (int)sizeof(unsigned long long), v[u], scaled_amp);
             }
         }
     }
@@ -909,11 +905,6 @@ __device__ inline void pair_entry(const PairStep<L> &P, int e, float2 &v, int &w
     wbyte = P.baseb + *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(P.wkeys) + (rel << 2));
 }
 
-__device__ inline void lds_add(unsigned long long *acc, int wbyte, unsigned long long v)
-{
-    atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(acc) + wbyte), v);
-}
-
 template <int L, int VT>
 __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, int cnt, int m_nrows,
                                   int m_bo, int m_nb, int m_bc0, int m_bc1, int m_eb, int m_base,
@@ -922,12 +913,14 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
     using S = TileShape<L>;
     const int lane = threadIdx.x & 63;
     // all loads issued together: rows past the pair's last re-read its first row, counted as empty
+    // (32-bit byte offsets from the array's base: the library keeps blk_off below 2^30 entries)
     int m_rs[S::TB], m_rc[S::TB];
+    const char *bo = reinterpret_cast<const char *>(a.blk_off);
 #pragma unroll
     for (int r = 0; r < S::TB; ++r) {
-        const int32_t *row = a.blk_off + m_bo + (r < m_nrows ? r : 0) * m_nb;
-        m_rs[r] = row[m_bc0];
-        m_rc[r] = row[m_bc1];
+        const uint32_t row = (uint32_t)(m_bo + (r < m_nrows ? r : 0) * m_nb);
+        m_rs[r] = *reinterpret_cast<const int32_t *>(bo + ((row + (uint32_t)m_bc0) << 2));
+        m_rc[r] = *reinterpret_cast<const int32_t *>(bo + ((row + (uint32_t)m_bc1) << 2));
     }
     int m_tot = 0;
 #pragma unroll
@@ -954,14 +947,14 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
             int w0, w1;
             pair_entry<L, VT>(P, e0, v0, w0);
             if (e1 < P.total) pair_entry<L, VT>(P, e1, v1, w1);
-            lds_add(acc, w0, packed_fixed(v0, P.sa));
-            if (e1 < P.total) lds_add(acc, w1, packed_fixed(v1, P.sa));
+            lds_add(acc, w0, v0, P.sa);
+            if (e1 < P.total) lds_add(acc, w1, v1, P.sa);
         }
         if (c + lane < P.total) {
             float2 v0;
             int w0;
             pair_entry<L, VT>(P, c + lane, v0, w0);
-            lds_add(acc, w0, packed_fixed(v0, P.sa));
+            lds_add(acc, w0, v0, P.sa);
         }
     }
 }
@@ -971,8 +964,7 @@ __device__ inline void walk_pairs(unsigned long long *acc, const TileArgs &a, in
 // scaling in FP64 and converting (for results above the FP32 normal range's floor).
 __device__ inline float2 fixed_value(unsigned long long w, int e2)
 {
-    const unsigned lo = (unsigned)w, hi = (unsigned)(w >> 32);
-    const int im = (int)lo, re = (int)(hi - (unsigned)(im >> 31));  // undoes packed_fixed
+    const int re = (int)(unsigned)w, im = (int)(unsigned)(w >> 32);
     return make_float2(ldexpf((float)re, e2), ldexpf((float)im, e2));
 }
 

@@ -53,7 +53,7 @@ def test_argument_validation_without_device():
 
 def test_lut_offsets_beyond_int32_rejected_before_allocation():
     """The superposition addresses kept entries and per-block offsets with 32-bit integers, so a
-    LUT whose tables hold 2^31 or more Haar blocks is refused while the geometry is computed, before
+    LUT whose tables hold 2^30 or more Haar blocks is refused while the geometry is computed, before
     any device memory is requested (no GPU here: an allocation attempt would fail differently).
     Here 16384 planes x 64 phase tables of up to 1008^2 pixels make ~1.7e10 blocks of 8 x 8, while
     gamma = 0.001 keeps only ~8e8 entries."""
@@ -61,7 +61,7 @@ def test_lut_offsets_beyond_int32_rejected_before_allocation():
     h = ctypes.c_void_p()
     prm = cgh.LutParams(n_depth=16384, levels=3, phases=1, gamma=0.001, max_window=1024).c()
     assert lib.wasabi_build_lut(ctypes.byref(prm), ctypes.byref(h), None) == cgh.CGH_EINVAL
-    assert b"2^31" in lib.cgh_last_error() and b"blocks" in lib.cgh_last_error()
+    assert b"2^30" in lib.cgh_last_error() and b"blocks" in lib.cgh_last_error()
     assert not h.value
     # too many kept coefficients: 8192 planes of 80^2 .. 1008^2 pixels (~3e9 in all), all kept
     prm = cgh.LutParams(n_depth=8192, levels=3, gamma=1.0, max_window=1024).c()
