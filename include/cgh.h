@@ -22,7 +22,10 @@
  *    reported by the call that launched it; faults that occur later surface at the caller's next
  *    synchronisation of the stream.
  *  - Scratch memory is taken from HIP's stream-ordered pool (hipMallocAsync on `stream`) and given
- *    back on the same stream before the call returns.
+ *    back on the same stream before the call returns.  Such a call made while `stream` is being
+ *    captured into a HIP graph returns CGH_EINVAL before it enqueues anything: graphs holding its
+ *    allocations as memory nodes are not supported.  wasabi_hologram_fused_noalloc (and the
+ *    server's jobs, whose scratch comes from their slots) allocate nothing and can be captured.
  */
 #ifndef CGH_H
 #define CGH_H

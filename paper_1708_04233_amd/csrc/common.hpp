@@ -34,7 +34,8 @@ int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 // Stream-ordered scratch: allocated from the device's default pool on `stream` and returned to
 // it on the same stream when the guard goes out of scope.
 // With an arena, allocations are carved (256-byte aligned) from that caller-owned device buffer
-// instead, and nothing is freed: work on `stream` orders the reuse of the arena.
+// instead, and nothing is freed: work on `stream` orders the reuse of the arena.  Without one, the
+// first allocation fails with CGH_EINVAL while `stream` is being captured into a HIP graph.
 class Scratch {
   public:
     explicit Scratch(hipStream_t s) : stream_(s) {}
@@ -48,6 +49,7 @@ class Scratch {
     std::vector<void *> ptrs_;
     char *arena_ = nullptr;
     size_t cap_ = 0, used_ = 0;
+    bool capture_checked_ = false;
 };
 
 // Keeps the default pool's memory cached between calls (release threshold = unlimited) and stops it

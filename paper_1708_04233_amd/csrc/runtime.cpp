@@ -35,6 +35,18 @@ int Scratch::alloc(void **p, size_t bytes)
         used_ += b;
         return CGH_OK;
     }
+    if (!capture_checked_) {
+        // Under stream capture the allocations and frees below would become graph memory nodes;
+        // replaying such a graph has crashed the host process here, so a capturing caller is
+        // refused before anything is enqueued (every call allocates before its first launch).
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        const hipError_t ce = hipStreamIsCapturing(stream_, &st);
+        if (ce != hipSuccess) return fail(CGH_EHIP, "hipStreamIsCapturing: %s", hipGetErrorString(ce));
+        if (st != hipStreamCaptureStatusNone)
+            return fail(CGH_EINVAL, "this call allocates stream-ordered scratch and cannot be captured into a HIP "
+                                    "graph; wasabi_hologram_fused_noalloc can");
+        capture_checked_ = true;
+    }
     if (bytes == 0) bytes = 256;
     hipError_t e = hipMallocAsync(p, bytes, stream_);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {

@@ -44,3 +44,25 @@ def test_graph_replay_matches_eager(gamma):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(u, eager), k
+
+
+def test_allocating_entry_point_refuses_capture():
+    """wasabi_hologram_fused takes its scratch from the stream-ordered pool; under capture it returns
+    CGH_EINVAL before enqueueing anything (graphs holding its allocations as memory nodes are not
+    supported), and the stream is usable afterwards."""
+    lut = cgh.wasabi_build_lut(cgh.LutParams(n_depth=8, levels=3, gamma=0.05, max_window=256,
+                                             z_min=20e-6, z_max=90e-6))
+    pts = torch.from_numpy(grid_points(3, 100, 256, 256, 8, 20e-6, 90e-6)).cuda()
+    q = cgh.wasabi_quantize(lut, pts)
+    u = torch.empty((256, 256), dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(cgh.CghError) as e:
+        with torch.cuda.graph(g):
+            cgh.wasabi_hologram_fused(lut, q, 0, 0, 256, 256, u=u)
+    assert e.value.code == cgh.CGH_EINVAL and "captured" in str(e.value)
+    torch.cuda.synchronize()
+    want = cgh.wasabi_hologram_fused(lut, q, 0, 0, 256, 256)   # outside capture: works as before
+    alone = cgh.wasabi_hologram_fused_noalloc(lut, q, 0, 0, 256, 256, u=u)
+    torch.cuda.synchronize()
+    assert torch.equal(alone, want)
