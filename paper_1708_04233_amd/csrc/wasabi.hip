@@ -56,8 +56,8 @@ struct TileGeom {
 // 8 XCDs in turn (b mod 8), each with its own L2, and XCD k takes the k-th of 8 equal runs of the
 // block's row-major tiles.  Bands measured faster for the sparse superposition of grids beyond
 // 4096 tiles (65536^2: 15.0 -> 14.2 ms, 16384^2: 6.32 -> 6.22 ms), slower for a single resident
-// block (2048^2: 0.34 -> 0.37 ms) and for the dense superposition and the inverse, which keep
-// row-major order.
+// block (2048^2: 0.34 -> 0.37 ms) and for the dense superposition and the inverse; the inverse
+// keeps row-major order, the dense superposition groups the tiles of a list cell (tile_of_cells).
 template <bool BANDS = false>
 __device__ inline void tile_of(int b, const TileGeom &g, int &ty, int &tx)
 {
@@ -73,6 +73,32 @@ __device__ inline void tile_of(int b, const TileGeom &g, int &ty, int &tx)
     const int t = i < NX * run ? (i % NX) * run + i / NX : i;
     ty = T * R + t / w;
     tx = T * C + t % w;
+}
+
+// Tile handled by workgroup b of the dense superposition when the lists are kept per cell of
+// sup x sup tiles (sup >= 2) and the window is a whole number of 32 x 32-tile blocks: each group of
+// 8 sup^2 consecutive workgroups takes 8 list cells, cell k of the group on XCD k (its workgroups
+// are b = k, k + 8, ... of the group, as workgroups go to the XCDs in turn).  The tiles of a cell
+// walk the same list in the same order at about the same time, and on one XCD they share one L2:
+// a tile's table window for one point overlaps the windows its neighbours read for the points
+// just before it.  Cells are taken in 32 x 32-tile blocks (as tile_of), row-major inside a block,
+// so with sup = 4 XCD k works down the block's k-th column of cells.  65536^2, 40 dB selectivity:
+// FP32 values 152 -> 122 ms, FP16 63 -> 49 ms (cells of 2 x 4 or 4 x 2 per XCD instead of a
+// column: 132 and 125 ms FP32).  Other grids use tile_of.
+__device__ inline void tile_of_cells(int b, const TileGeom &g, int &ty, int &tx)
+{
+    const int sup = g.cell / kT;
+    if (sup < 2 || g.ntx % 32 || g.nty % 32) {
+        tile_of(b, g, ty, tx);
+        return;
+    }
+    const int per = sup * sup, cw = 32 / sup;
+    const int grp = b / (8 * per), k = b % 8, j = (b % (8 * per)) / 8;
+    const int cell = grp * 8 + k;
+    const int blk = cell / (cw * cw), cib = cell % (cw * cw);
+    const int BR = blk / (g.ntx / 32), BC = blk % (g.ntx / 32);
+    ty = BR * 32 + (cib / cw) * sup + j / sup;
+    tx = BC * 32 + (cib % cw) * sup + j % sup;
 }
 
 // List cells touched by the occupied part of point p's table; false if none.
@@ -1224,7 +1250,7 @@ void dense_tile_kernel(TileArgs a)
     __shared__ float sbuf[2 * S::N];
     const int tile = blockIdx.x;
     int ty, tx;
-    tile_of(tile, a.g, ty, tx);
+    tile_of_cells(tile, a.g, ty, tx);
     const int th = min(kT, a.g.ny - ty * kT), tw = min(kT, a.g.nx - tx * kT);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1725,10 +1751,20 @@ int bin_points(const wasabi_lut *lut, const wasabi_point *pts, int64_t n, const 
     return CGH_OK;
 }
 
+// LDS a dense FP32 workgroup reserves when the tiles are not paced, so that at most two tiles share
+// a CU (four fit otherwise).  Without pacing the resident tiles cover a region of the grid that
+// grows with their number, and so does the table data they read at once; with FP32 values that
+// data overflows the L2s.  65536^2, 40 dB selectivity: four tiles per CU 122.7 ms, three 105.5 ms,
+// two 96.4 ms, one 121.9 ms.  FP16 values (half the bytes) run best with four (49.8, 53.6, 67.1 ms
+// with four, three, two), so they keep the default.
+constexpr size_t kDenseF32TileLds = 62 * 1024;
+
 template <int L, int MODE>
 void launch_dense_l(int vt, const TileArgs &a, unsigned grid, hipStream_t s)
 {
-    if (vt == CGH_F32) hipLaunchKernelGGL((dense_tile_kernel<L, CGH_F32, MODE>), dim3(grid), dim3(kDenseThreads), 0, s, a);
+    constexpr size_t stat = sizeof(float) * 2 * TileShape<L>::N + sizeof(int);  // the kernel's own LDS
+    const size_t pad = a.plane_done == nullptr && stat < kDenseF32TileLds ? kDenseF32TileLds - stat : 0;
+    if (vt == CGH_F32) hipLaunchKernelGGL((dense_tile_kernel<L, CGH_F32, MODE>), dim3(grid), dim3(kDenseThreads), pad, s, a);
     else if (vt == CGH_F16) hipLaunchKernelGGL((dense_tile_kernel<L, CGH_F16, MODE>), dim3(grid), dim3(kDenseThreads), 0, s, a);
     else hipLaunchKernelGGL((dense_tile_kernel<L, CGH_BF16, MODE>), dim3(grid), dim3(kDenseThreads), 0, s, a);
 }
