@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--sub", type=int, default=None, help="sub-hologram side for the coiflet workload")
     ap.add_argument("--serve-jobs", type=int, default=None,
                     help="jobs per serving run (default 200 beside the headline line, 1000 for --workload serve)")
-    ap.add_argument("--cpu-windows", type=int, default=192,
+    ap.add_argument("--cpu-windows", type=int, default=384,
                     help="512^2 windows the CPU oracle computes for the baseline of the headline line")
     ap.add_argument("--core", action="store_true",
                     help="headline line: only the 65536^2 runs and its direct sum (no 2048^2, serving, 512^2 or "
