@@ -170,9 +170,12 @@ def test_65536_40db_selectivity_windows(orc, dtype):
     B = 1 << w["levels"]
     pts = height_field_points(w["seed"], w["n"], w["nx"], B, w["z_lo"], w["z_hi"])
     q = cgh.wasabi_quantize(lut, torch.from_numpy(pts).cuda())
-    u = torch.empty((w["ny"], w["nx"]), dtype=torch.complex64, device="cuda")
+    u = torch.full((w["ny"], w["nx"]), complex(float("nan"), float("nan")), dtype=torch.complex64, device="cuda")
     cgh.wasabi_hologram_fused(lut, q, 0, 0, w["nx"], w["ny"], u=u)
     torch.cuda.synchronize()
+    # every tile was written (the launch hands tiles to workgroups cell by cell, grouped per XCD)
+    for r0 in range(0, w["ny"], 4096):
+        assert bool(torch.isfinite(torch.view_as_real(u[r0:r0 + 4096])).all()), r0
     check_windows(orc, olut, orc.quantize(pts, olut.params), u, w["nx"], B, seed=8, k=1)
     del u
     torch.cuda.empty_cache()

@@ -259,7 +259,10 @@ def test_repeated_runs_bitwise(gamma, side, n):
     lut = cgh.wasabi_build_lut(cgh.LutParams(n_depth=64, levels=3, gamma=gamma, max_window=1024))
     pts = grid_points(70, n, side, side, 8, 0.1e-3, 1.5e-3)
     q = cgh.wasabi_quantize(lut, torch.from_numpy(pts).cuda())
-    first = cgh.wasabi_hologram_fused(lut, q, 0, 0, side, side).clone()
+    nan = complex(float("nan"), float("nan"))
+    first = cgh.wasabi_hologram_fused(lut, q, 0, 0, side, side,
+                                      u=torch.full((side, side), nan, dtype=torch.complex64, device="cuda")).clone()
+    assert bool(torch.isfinite(torch.view_as_real(first)).all())   # every tile written
     for _ in range(3):
         again = cgh.wasabi_hologram_fused(lut, q, 0, 0, side, side)
         torch.cuda.synchronize()
@@ -268,3 +271,5 @@ def test_repeated_runs_bitwise(gamma, side, n):
     psi1 = cgh.wasabi_superpose(lut, q, 0, 0, side, side)
     torch.cuda.synchronize()
     assert torch.equal(psi0, psi1)
+    # the separate path (psi, then the inverse, whose tiles go in row-major order) gives the same bits
+    assert torch.equal(cgh.wasabi_idwt(psi0, 3), first)
